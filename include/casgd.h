@@ -1,0 +1,244 @@
+/*
+ * casgd.h -- C ABI of libcasgd: s-step (communication-avoiding) mini-batch SGD
+ * for L2-regularised logistic regression on AMD Instinct MI355X (gfx950).
+ *
+ * Method: "Mixed-Precision Communication-Avoiding SGD for Generalized Linear
+ * Models on GPUs". One outer iteration (Algorithm 1) samples s blocks of b
+ * rows Y = X[I,:], forms the margins r = Y x and the strict block-lower part
+ * of the Gram matrix G = Y Y^T, runs the s dependent residual corrections
+ * (Algorithm 1, inner loop) and applies one update x += (eta/b) Y^T delta.
+ * The L2 term (lambda/2)||x||^2, which the paper does not have, is folded in
+ * as the per-step decay beta = 1 - eta*lambda:
+ *     z_j   = beta^j r_j + (eta/b) sum_{i<j} beta^(j-1-i) G_{j,i} delta_i
+ *     delta_j = y_{I_j} / (1 + exp(y_{I_j} z_j))      (= y (1 - sigma(y z)), Sec. 3.1)
+ *     x    <- beta^s x + (eta/b) Y^T c,   c_i = beta^(s-1-i) delta_i.
+ * This is exactly s plain SGD steps on the same samples (Sec. 5.1,
+ * Assumption 6: the exact block is the composition of s mini-batch steps).
+ *
+ * Sampling (Algorithm 1, first step: i.i.d. uniform with replacement; the
+ * paper does not fix a generator): sample number t of stream `seed` is
+ * SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) output t, i.e.
+ * mix(seed + (t+1) * 0x9E3779B97F4A7C15), mapped to a row by the high 64 bits
+ * of its 128-bit product with m. Outer iteration h uses samples
+ * h*s*b ... (h+1)*s*b - 1 and block j of it the b samples starting at
+ * h*s*b + j*b, so plain SGD (s = 1) visits the same rows in the same order
+ * for every s.
+ *
+ * Conventions for every entry point:
+ *  - Pointers marked (device) are device memory of the current HIP device;
+ *    pointers marked (host) are host memory. The caller owns every buffer;
+ *    the library never allocates or frees device memory. Scratch memory comes
+ *    from the caller's workspace `ws` (device, 256-byte aligned), sized by the
+ *    matching *_workspace_size call, and is only valid for the problem shape
+ *    it was sized for.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream). Work
+ *    is enqueued and the call returns without waiting.
+ *  - Argument errors are reported synchronously by the return value, with a
+ *    message from casgd_last_error() (per thread). Device-side conditions
+ *    (non-finite values, a grid barrier that did not complete) are recorded
+ *    in the workspace and reported by casgd_check() after the stream has been
+ *    synchronised. No C++ exception crosses this interface.
+ *  - Calls on distinct workspaces may run concurrently; calls sharing one
+ *    workspace must be ordered on one stream.
+ *  - Results are bitwise reproducible for a fixed (problem, b, s, seed,
+ *    launch configuration); reductions use fixed orders, never atomics on
+ *    floating-point data.
+ */
+#ifndef CASGD_H
+#define CASGD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t casgd_status;
+enum {
+    CASGD_OK = 0,
+    CASGD_EINVAL = -1,       /* invalid argument */
+    CASGD_EUNSUPPORTED = -2, /* valid but not supported (shape, dtype, limit) */
+    CASGD_ENOMEM = -3,       /* workspace too small */
+    CASGD_EDEVICE = -4,      /* HIP runtime error */
+    CASGD_ENONFINITE = -5,   /* a margin, residual or weight became NaN/Inf */
+    CASGD_ETIMEOUT = -6      /* a grid barrier of the fused kernel timed out */
+};
+
+/* Storage formats of X (Table 1 storage slot u_A). */
+enum {
+    CASGD_F32 = 0,      /* IEEE binary32 */
+    CASGD_BF16 = 1,     /* bfloat16 bits (uint16) */
+    CASGD_F16 = 2,      /* IEEE binary16 */
+    CASGD_FP8E4M3 = 3   /* OCP FP8 E4M3 (bias 7, max 448, no Inf); needs row_scale */
+};
+
+/* Matrix layouts. */
+enum { CASGD_DENSE = 0, CASGD_CSR = 1 };
+
+/*
+ * A feature matrix X with m rows (samples) and n columns (features).
+ * DENSE: `values` (device) holds m rows of `ld` elements of `dtype`, row i at
+ *   values + i*ld; ld >= n, ld*elementsize a multiple of 16 bytes and the base
+ *   16-byte aligned. Columns n..ld-1 are never read.
+ * CSR: `row_ptr` (device, int64, m+1), `col_idx` (device, int32, nnz, sorted
+ *   within each row, < n) and `values` (device, FP32, nnz); dtype must be
+ *   CASGD_F32; ld is ignored.
+ * `row_scale` (device, FP32, m) or NULL: the stored row i represents
+ *   row_scale[i] * values[i,:]. Required for CASGD_FP8E4M3, optional otherwise.
+ */
+typedef struct {
+    int64_t m, n, ld;
+    int32_t dtype;
+    int32_t layout;
+    const void *values;
+    const float *row_scale;
+    const int64_t *row_ptr;
+    const int32_t *col_idx;
+    int64_t nnz;
+} casgd_matrix;
+
+/* Execution options; a NULL pointer means all defaults (zeros). */
+typedef struct {
+    /* Precision of the inner residual corrections (slot u_c, Sec. 5.2):
+     * 0 = automatic (FP64 when s*b >= 512, else FP32), 32 = FP32, 64 = FP64. */
+    int32_t recur_prec;
+    /* 0 = automatic, 1 = one fused persistent launch for the whole fit,
+     * 2 = one launch per phase, stream ordered. */
+    int32_t exec_mode;
+    /* Snapshots: when > 0, after every `snapshot_every` outer iterations the
+     * current x is copied to x_history (device, FP32, row k = snapshot k,
+     * n_outer / snapshot_every rows of n) and, if t_history (device, int64)
+     * is not NULL, the device wall clock (100 MHz ticks) to t_history[k]. */
+    int64_t snapshot_every;
+    float *x_history;
+    int64_t *t_history;
+    /* Grid-barrier spin limit for the fused kernel (0 = default, about 2 s). */
+    int64_t spin_limit;
+    /* Tuning knobs of the fused kernel (0 = automatic):
+     * fused_variant 1 = every update workgroup runs the recurrence itself
+     *   (one grid barrier per outer iteration; for small s*b),
+     * fused_variant 2 = one workgroup runs the recurrence while the others
+     *   compute the next outer iteration's Gram (two barriers);
+     * grid_blocks = number of workgroups of the fused launch (capped at the
+     *   number that can be resident). */
+    int32_t fused_variant;
+    int32_t grid_blocks;
+} casgd_opts;
+
+const char *casgd_status_string(casgd_status st);
+/* Message of the last failing call on this thread ("" if none). */
+const char *casgd_last_error(void);
+/* Library version as 10000*major + 100*minor + patch. */
+int32_t casgd_version(void);
+
+/* ------------------------------------------------------------ one problem */
+
+/* Workspace bytes for casgd_step / casgd_fit on X with these b, s. */
+casgd_status casgd_workspace_size(const casgd_matrix *X, int32_t b, int32_t s,
+                                  size_t *bytes);
+
+/* Clear the device flags in a workspace (non-finite, timeout). Enqueued. */
+casgd_status casgd_reset(void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * One outer iteration (Algorithm 1 with L2 decay) at index `outer_iter`,
+ * updating x (device, FP32, n) in place. y (device, FP32, m) holds +-1 labels.
+ * eta > 0, lambda >= 0, b >= 1, s >= 1, s*b <= 4096. Stateless: the sample
+ * set comes from (seed, outer_iter), so a sequence of calls with increasing
+ * outer_iter equals one casgd_fit.
+ */
+casgd_status casgd_step(const casgd_matrix *X, const float *y, float *x, double eta,
+                        double lambda, int32_t b, int32_t s, uint64_t seed,
+                        uint64_t outer_iter, const casgd_opts *opts, void *ws,
+                        size_t ws_bytes, void *stream);
+
+/* Outer iterations outer_begin .. outer_begin + n_outer - 1. */
+casgd_status casgd_fit(const casgd_matrix *X, const float *y, float *x, double eta,
+                       double lambda, int32_t b, int32_t s, uint64_t seed,
+                       uint64_t outer_begin, int64_t n_outer, const casgd_opts *opts,
+                       void *ws, size_t ws_bytes, void *stream);
+
+/* Reports the device flags of a workspace after synchronising `stream`:
+ * CASGD_OK, CASGD_ENONFINITE or CASGD_ETIMEOUT. */
+casgd_status casgd_check(const void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------- pieces of the iteration */
+
+/* Sample rows (Algorithm 1, first step): out[q] = row of sample t0+q. */
+casgd_status casgd_sample_indices(uint64_t seed, uint64_t t0, int64_t count, int64_t m,
+                                  int64_t *out, void *stream);
+
+/*
+ * Margins and Gram of outer iteration `outer_iter` (Algorithm 1, margin and
+ * Gram steps): r (device, FP32, s*b) = Y x and G (device, FP32, s*b x s*b,
+ * row-major) with the strict block-lower entries G[t][u] = Y_t . Y_u,
+ * block(u) < block(t), written; other entries are left untouched.
+ */
+casgd_status casgd_gram_margin(const casgd_matrix *X, const float *x, int32_t b,
+                               int32_t s, uint64_t seed, uint64_t outer_iter, float *G,
+                               float *r, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * The s residual corrections (Algorithm 1, inner loop, with decay) from
+ * device inputs G (FP32 s*b x s*b row-major, strict block-lower part read),
+ * r (FP32 s*b) and labels yI (FP32 s*b); writes c (device, FP32, s*b) with
+ * c_t = beta^(s-1-j) delta_t for t in block j, and delta (device, FP32, s*b)
+ * if not NULL. prec: 0 auto, 32, 64 as casgd_opts.recur_prec.
+ */
+casgd_status casgd_recurrence(const float *G, const float *r, const float *yI, int32_t b,
+                              int32_t s, double eta, double lambda, int32_t prec,
+                              float *c, float *delta, void *stream);
+
+/* x <- beta^s x + (eta/b) Y^T c for outer iteration `outer_iter` (Algorithm 1,
+ * gradient and update steps, fused). c: device FP32 s*b (row scales are
+ * applied by the library). */
+casgd_status casgd_update(const casgd_matrix *X, float *x, const float *c, int32_t b,
+                          int32_t s, uint64_t seed, uint64_t outer_iter, double eta,
+                          double lambda, void *stream);
+
+/* ------------------------------------------------------- storage formats */
+
+/*
+ * Convert an FP32 matrix (device, m x ld_src) to storage `dtype`
+ * (Table 1, storage precision u_A): dst (device, m x ld_dst elements of dtype).
+ * BF16 and F16 round to nearest even; FP8-E4M3 uses per-row scales
+ * scale_i = amax_i / 448 (FP32), stores e4m3(x * (448 / amax_i)) rounded to
+ * nearest even with saturation at +-448, and writes row_scale (device, m);
+ * an all-zero row gets scale 1. BF16, F16 and F32 are not scaled: row_scale
+ * may be NULL, and if it is not it is filled with 1. Columns n..ld_dst-1 of
+ * dst are set to zero.
+ */
+casgd_status casgd_quantize(const float *src, int64_t m, int64_t n, int64_t ld_src,
+                            int32_t dtype, void *dst, int64_t ld_dst, float *row_scale,
+                            void *stream);
+
+/* --------------------------------------------------- measurement support */
+
+/*
+ * Mean logistic loss m^-1 sum_i log(1 + exp(-y_i a_i^T x)) (Sec. 2.1) for
+ * `count` weight vectors x_k = xs + k*x_stride (device, FP32, n each);
+ * out (device, FP64, count). Dense X (any dtype, row scales applied) or CSR.
+ * Margins accumulate in FP32, the loss terms and their sum in FP64, in a fixed
+ * order. ws (device) must hold casgd_logloss_workspace_size() bytes.
+ */
+size_t casgd_logloss_workspace_size(int64_t count);
+casgd_status casgd_logloss(const casgd_matrix *X, const float *y, const float *xs,
+                           int64_t count, int64_t x_stride, double *out, void *ws,
+                           size_t ws_bytes, void *stream);
+
+/*
+ * Per-column statistics (device, FP32, n x 4 row-major): mean, population
+ * variance, fraction of nonzeros and max |value| over the m rows, with row
+ * scales applied. Dense X (any dtype) or CSR. ws (device) must hold
+ * casgd_colstats_workspace_size(X) bytes.
+ */
+size_t casgd_colstats_workspace_size(const casgd_matrix *X);
+casgd_status casgd_colstats(const casgd_matrix *X, float *stats, void *ws, size_t ws_bytes,
+                            void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CASGD_H */

@@ -1,0 +1,243 @@
+"""MI355X-native s-step (communication-avoiding) SGD for L2-regularised logistic
+regression.
+
+Python binding of libcasgd (``include/casgd.h``). Every function here only
+marshals arguments: tensors are passed to the C ABI by device pointer and the
+current HIP stream; all computation happens in the library's HIP kernels.
+PyTorch is used for device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import BF16, CSR, DENSE, F16, F32, FP8E4M3  # noqa: F401
+
+__all__ = [
+    "CasgdError", "dense_matrix", "csr_matrix", "opts", "workspace",
+    "casgd_workspace_size", "casgd_reset", "casgd_step", "casgd_fit", "casgd_check",
+    "casgd_sample_indices", "casgd_gram_margin", "casgd_recurrence", "casgd_update",
+    "casgd_quantize", "casgd_logloss", "casgd_colstats", "casgd_version",
+]
+
+
+class CasgdError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        super().__init__(f"{_lib.STATUS_NAMES.get(status, status)}: {message}")
+
+
+def _L():
+    return _lib.load()
+
+
+def _check(rc: int) -> None:
+    if rc != 0:
+        raise CasgdError(rc, _L().casgd_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+_DTYPES = {}
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if not _DTYPES:
+        _DTYPES.update({torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16,
+                        torch.uint8: FP8E4M3, torch.float8_e4m3fn: FP8E4M3})
+    return _DTYPES[t.dtype]
+
+
+class MatrixRef:
+    """A casgd_matrix plus references that keep its tensors alive."""
+
+    def __init__(self, struct: _lib.Matrix, keep: tuple):
+        self.struct = struct
+        self._keep = keep
+
+    @property
+    def m(self) -> int:
+        return self.struct.m
+
+    @property
+    def n(self) -> int:
+        return self.struct.n
+
+    @property
+    def dtype(self) -> int:
+        return self.struct.dtype
+
+    def ref(self):
+        return ctypes.byref(self.struct)
+
+
+def dense_matrix(values, row_scale=None, n: int | None = None) -> MatrixRef:
+    """Dense row-major X: ``values`` (m x ld device tensor; float32, bfloat16,
+    float16, or uint8/float8_e4m3fn holding E4M3 codes); ``n`` <= ld valid
+    columns (default ld)."""
+    assert values.dim() == 2 and values.is_cuda and values.stride(1) == 1
+    m, ld = values.shape[0], values.stride(0)
+    s = _lib.Matrix(m=m, n=(n if n is not None else values.shape[1]), ld=ld,
+                    dtype=_dtype_code(values), layout=DENSE, values=_ptr(values),
+                    row_scale=_ptr(row_scale), row_ptr=None, col_idx=None, nnz=0)
+    return MatrixRef(s, (values, row_scale))
+
+
+def csr_matrix(row_ptr, col_idx, values, n: int) -> MatrixRef:
+    """CSR X: row_ptr (int64, m+1), col_idx (int32, sorted per row), values (float32)."""
+    torch = _torch()
+    assert row_ptr.dtype == torch.int64 and col_idx.dtype == torch.int32
+    assert values.dtype == torch.float32
+    s = _lib.Matrix(m=row_ptr.numel() - 1, n=n, ld=0, dtype=F32, layout=CSR,
+                    values=_ptr(values), row_scale=None, row_ptr=_ptr(row_ptr),
+                    col_idx=_ptr(col_idx), nnz=values.numel())
+    return MatrixRef(s, (row_ptr, col_idx, values))
+
+
+def opts(recur_prec: int = 0, exec_mode: int = 0, snapshot_every: int = 0, x_history=None,
+         t_history=None, spin_limit: int = 0, fused_variant: int = 0, grid_blocks: int = 0):
+    o = _lib.Opts(recur_prec=recur_prec, exec_mode=exec_mode, snapshot_every=snapshot_every,
+                  x_history=_ptr(x_history), t_history=_ptr(t_history), spin_limit=spin_limit,
+                  fused_variant=fused_variant, grid_blocks=grid_blocks)
+    o._keep = (x_history, t_history)
+    return o
+
+
+def casgd_version() -> int:
+    return int(_L().casgd_version())
+
+
+def casgd_workspace_size(X: MatrixRef, b: int, s: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(_L().casgd_workspace_size(X.ref(), b, s, ctypes.byref(out)))
+    return int(out.value)
+
+
+def workspace(nbytes: int, device=None):
+    """A zeroed, 256-byte aligned device buffer of nbytes (torch allocation)."""
+    torch = _torch()
+    t = torch.zeros(max(nbytes, 256) + 256, dtype=torch.uint8, device=device or "cuda")
+    off = (-t.data_ptr()) % 256
+    return t[off:off + max(nbytes, 256)]
+
+
+def _ws(ws, need: int):
+    if ws is None:
+        ws = workspace(need)
+    return ws, ws.numel()
+
+
+def casgd_reset(ws, stream=None) -> None:
+    _check(_L().casgd_reset(_ptr(ws), ws.numel(), _stream(stream)))
+
+
+def casgd_check(ws, stream=None) -> None:
+    _check(_L().casgd_check(_ptr(ws), ws.numel(), _stream(stream)))
+
+
+def _opts_ref(o):
+    return None if o is None else ctypes.byref(o)
+
+
+def casgd_fit(X: MatrixRef, y, x, eta: float, lam: float, b: int, s: int, seed: int,
+              outer_begin: int = 0, n_outer: int = 1, opts=None, ws=None, stream=None):
+    """Outer iterations outer_begin .. outer_begin + n_outer - 1 on x (in place)."""
+    ws, nb = _ws(ws, casgd_workspace_size(X, b, s))
+    _check(_L().casgd_fit(X.ref(), _ptr(y), _ptr(x), eta, lam, b, s, seed, outer_begin,
+                          n_outer, _opts_ref(opts), _ptr(ws), nb, _stream(stream)))
+    return ws
+
+
+def casgd_step(X: MatrixRef, y, x, eta: float, lam: float, b: int, s: int, seed: int,
+               outer_iter: int, opts=None, ws=None, stream=None):
+    ws, nb = _ws(ws, casgd_workspace_size(X, b, s))
+    _check(_L().casgd_step(X.ref(), _ptr(y), _ptr(x), eta, lam, b, s, seed, outer_iter,
+                           _opts_ref(opts), _ptr(ws), nb, _stream(stream)))
+    return ws
+
+
+def casgd_sample_indices(seed: int, t0: int, count: int, m: int, out=None, stream=None):
+    torch = _torch()
+    out = out if out is not None else torch.empty(count, dtype=torch.int64, device="cuda")
+    _check(_L().casgd_sample_indices(seed, t0, count, m, _ptr(out), _stream(stream)))
+    return out
+
+
+def casgd_gram_margin(X: MatrixRef, x, b: int, s: int, seed: int, outer_iter: int, G=None,
+                      r=None, ws=None, stream=None):
+    torch = _torch()
+    sb = s * b
+    G = G if G is not None else torch.zeros(sb, sb, dtype=torch.float32, device="cuda")
+    r = r if r is not None else torch.zeros(sb, dtype=torch.float32, device="cuda")
+    ws, nb = _ws(ws, casgd_workspace_size(X, b, s))
+    _check(_L().casgd_gram_margin(X.ref(), _ptr(x), b, s, seed, outer_iter, _ptr(G), _ptr(r),
+                                  _ptr(ws), nb, _stream(stream)))
+    return G, r
+
+
+def casgd_recurrence(G, r, yI, b: int, s: int, eta: float, lam: float, prec: int = 0,
+                     c=None, delta=None, stream=None):
+    torch = _torch()
+    c = c if c is not None else torch.empty(s * b, dtype=torch.float32, device="cuda")
+    _check(_L().casgd_recurrence(_ptr(G), _ptr(r), _ptr(yI), b, s, eta, lam, prec, _ptr(c),
+                                 _ptr(delta), _stream(stream)))
+    return c
+
+
+def casgd_update(X: MatrixRef, x, c, b: int, s: int, seed: int, outer_iter: int, eta: float,
+                 lam: float, stream=None):
+    _check(_L().casgd_update(X.ref(), _ptr(x), _ptr(c), b, s, seed, outer_iter, eta, lam,
+                             _stream(stream)))
+    return x
+
+
+def casgd_quantize(src, dtype: int, ld_dst: int | None = None, stream=None):
+    """Convert an FP32 (m x n) device tensor to storage dtype; returns
+    (stored tensor m x ld_dst, row_scale or None)."""
+    torch = _torch()
+    m, n = src.shape
+    vec = {F32: 4, BF16: 8, F16: 8, FP8E4M3: 16}[dtype]
+    ld = ld_dst or ((n + vec - 1) // vec * vec)
+    tdt = {F32: torch.float32, BF16: torch.bfloat16, F16: torch.float16,
+           FP8E4M3: torch.uint8}[dtype]
+    dst = torch.empty(m, ld, dtype=tdt, device=src.device)
+    scale = torch.empty(m, dtype=torch.float32, device=src.device) if dtype == FP8E4M3 else None
+    _check(_L().casgd_quantize(_ptr(src), m, n, src.stride(0), dtype, _ptr(dst), ld, _ptr(scale),
+                               _stream(stream)))
+    return dst, scale
+
+
+def casgd_logloss(X: MatrixRef, y, xs, stream=None):
+    """Mean logistic loss for each row of xs (k x n) or for a single x (n)."""
+    torch = _torch()
+    xs2 = xs if xs.dim() == 2 else xs.view(1, -1)
+    count = xs2.shape[0]
+    out = torch.empty(count, dtype=torch.float64, device="cuda")
+    need = int(_L().casgd_logloss_workspace_size(count))
+    ws = workspace(need)
+    _check(_L().casgd_logloss(X.ref(), _ptr(y), _ptr(xs2), count, xs2.stride(0), _ptr(out),
+                              _ptr(ws), ws.numel(), _stream(stream)))
+    return out if xs.dim() == 2 else out[0]
+
+
+def casgd_colstats(X: MatrixRef, stream=None):
+    torch = _torch()
+    stats = torch.empty(X.n, 4, dtype=torch.float32, device="cuda")
+    need = int(_L().casgd_colstats_workspace_size(X.ref()))
+    ws = workspace(need)
+    _check(_L().casgd_colstats(X.ref(), _ptr(stats), _ptr(ws), ws.numel(), _stream(stream)))
+    return stats

@@ -1,0 +1,92 @@
+"""ctypes declarations of the libcasgd C ABI (``include/casgd.h``).
+
+Loading fails loudly when the shared library has not been built: there is
+no fallback implementation of any entry point.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcasgd.so")
+
+c_i32, c_i64, c_u64, c_dbl, c_vp, c_sz = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
+                                          ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t)
+
+CASGD_OK = 0
+STATUS_NAMES = {0: "CASGD_OK", -1: "CASGD_EINVAL", -2: "CASGD_EUNSUPPORTED", -3: "CASGD_ENOMEM",
+                -4: "CASGD_EDEVICE", -5: "CASGD_ENONFINITE", -6: "CASGD_ETIMEOUT"}
+
+F32, BF16, F16, FP8E4M3 = 0, 1, 2, 3
+DENSE, CSR = 0, 1
+
+
+class Matrix(ctypes.Structure):
+    _fields_ = [("m", c_i64), ("n", c_i64), ("ld", c_i64), ("dtype", c_i32), ("layout", c_i32),
+                ("values", c_vp), ("row_scale", c_vp), ("row_ptr", c_vp), ("col_idx", c_vp),
+                ("nnz", c_i64)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("recur_prec", c_i32), ("exec_mode", c_i32), ("snapshot_every", c_i64),
+                ("x_history", c_vp), ("t_history", c_vp), ("spin_limit", c_i64),
+                ("fused_variant", c_i32), ("grid_blocks", c_i32)]
+
+
+PM = ctypes.POINTER(Matrix)
+PO = ctypes.POINTER(Opts)
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "casgd_status_string": (ctypes.c_char_p, [c_i32]),
+    "casgd_last_error": (ctypes.c_char_p, []),
+    "casgd_version": (c_i32, []),
+    "casgd_workspace_size": (c_i32, [PM, c_i32, c_i32, ctypes.POINTER(c_sz)]),
+    "casgd_reset": (c_i32, [c_vp, c_sz, c_vp]),
+    "casgd_step": (c_i32, [PM, c_vp, c_vp, c_dbl, c_dbl, c_i32, c_i32, c_u64, c_u64, PO, c_vp,
+                           c_sz, c_vp]),
+    "casgd_fit": (c_i32, [PM, c_vp, c_vp, c_dbl, c_dbl, c_i32, c_i32, c_u64, c_u64, c_i64, PO,
+                          c_vp, c_sz, c_vp]),
+    "casgd_check": (c_i32, [c_vp, c_sz, c_vp]),
+    "casgd_sample_indices": (c_i32, [c_u64, c_u64, c_i64, c_i64, c_vp, c_vp]),
+    "casgd_gram_margin": (c_i32, [PM, c_vp, c_i32, c_i32, c_u64, c_u64, c_vp, c_vp, c_vp, c_sz,
+                                  c_vp]),
+    "casgd_recurrence": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_dbl, c_dbl, c_i32, c_vp, c_vp,
+                                 c_vp]),
+    "casgd_update": (c_i32, [PM, c_vp, c_vp, c_i32, c_i32, c_u64, c_u64, c_dbl, c_dbl, c_vp]),
+    "casgd_quantize": (c_i32, [c_vp, c_i64, c_i64, c_i64, c_i32, c_vp, c_i64, c_vp, c_vp]),
+    "casgd_logloss_workspace_size": (c_sz, [c_i64]),
+    "casgd_logloss": (c_i32, [PM, c_vp, c_vp, c_i64, c_i64, c_vp, c_vp, c_sz, c_vp]),
+    "casgd_colstats_workspace_size": (c_sz, [PM]),
+    "casgd_colstats": (c_i32, [PM, c_vp, c_vp, c_sz, c_vp]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libcasgd.so and declare every entry point; raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is not built; run `python -m paper_2606_18463_amd.build` "
+            "(or __graft_entry__.build()) first")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def header_symbols() -> list[str]:
+    """Function names declared in include/casgd.h."""
+    import re
+    hdr = os.path.join(os.path.dirname(HERE), "include", "casgd.h")
+    txt = open(hdr).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(casgd_[a-z0-9_]+)\s*\(", txt)))

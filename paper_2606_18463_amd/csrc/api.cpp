@@ -1,0 +1,492 @@
+// C ABI of libcasgd: argument validation, workspace layout and dispatch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "internal.hpp"
+#include "misc.hpp"
+
+namespace casgd {
+
+static thread_local std::string t_err;
+
+void set_error(const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    t_err = buf;
+}
+
+casgd_status hip_fail(hipError_t e, const char* what) {
+    set_error("%s failed: %s", what, hipGetErrorString(e));
+    return CASGD_EDEVICE;
+}
+
+int dtype_bytes(int dt) {
+    switch (dt) {
+        case CASGD_F32: return 4;
+        case CASGD_BF16: return 2;
+        case CASGD_F16: return 2;
+        case CASGD_FP8E4M3: return 1;
+        default: return 0;
+    }
+}
+
+int dtype_vec(int dt) { return 16 / dtype_bytes(dt); }
+int slice_width_of(int dt) { return kLPR * dtype_vec(dt); }
+
+int device_cus() {
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (!cached[dev]) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+        cached[dev] = cus;
+    }
+    return cached[dev];
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+bool dense_layout(int64_t n, int dtype, int b, int s, DenseLayout* L) {
+    const int sb = s * b;
+    L->sb = sb;
+    L->ts = (sb + kTile - 1) / kTile;
+    L->ntiles = L->ts * (L->ts + 1) / 2;
+    int needed = 0;
+    for (int TJ = 0; TJ < L->ts; ++TJ)
+        for (int TI = 0; TI <= TJ; ++TI) {
+            const int rlast = std::min(TJ * kTile + kTile - 1, sb - 1);
+            if ((TI * kTile) / b < rlast / b) ++needed;
+        }
+    L->needed = needed;
+    const int kstep = 4 * dtype_vec(dtype);
+    int ksplit = 1;
+    if (s > 1 && needed > 0) {
+        const int target = 2048;  // waves: about two per SIMD of the chip
+        const int kmax = (int)std::max<int64_t>(1, n / 256);
+        ksplit = std::max(1, std::min(target / needed, kmax));
+    }
+    int64_t kchunk = (n + ksplit - 1) / ksplit;
+    kchunk = (kchunk + kstep - 1) / kstep * kstep;
+    ksplit = (int)((n + kchunk - 1) / kchunk);
+    L->ksplit = std::max(1, ksplit);
+    L->kchunk = kchunk;
+    const int kw = slice_width_of(dtype);
+    L->nslices = (int)((n + kw - 1) / kw);
+
+    size_t off = 0;
+    L->off_flags = off;
+    off = align256(off + FLAG_WORDS * 4);
+    L->off_tilecnt = off;
+    off = align256(off + (size_t)L->ntiles * 4);
+    const size_t gbytes = s > 1 ? (size_t)sb * sb * 4 : 0;
+    L->off_G0 = off;
+    off = align256(off + gbytes);
+    L->off_G1 = off;
+    off = align256(off + gbytes);
+    L->off_Gpart = off;
+    if (s > 1 && L->ksplit > 1) off = align256(off + (size_t)L->ntiles * L->ksplit * 4096 * 4);
+    L->off_rp0 = off;
+    off = align256(off + (size_t)L->nslices * sb * 4);
+    L->off_rp1 = off;
+    off = align256(off + (size_t)L->nslices * sb * 4);
+    L->off_c = off;
+    off = align256(off + (size_t)sb * 4);
+    L->off_r = off;
+    off = align256(off + (size_t)sb * 4);
+    L->off_y = off;
+    off = align256(off + (size_t)sb * 4);
+    L->off_d = off;
+    off = align256(off + (size_t)sb * 4);
+    L->total = off;
+    return true;
+}
+
+void dense_bind(const DenseLayout& L, void* ws, Dense* P) {
+    char* w = static_cast<char*>(ws);
+    P->sb = L.sb;
+    P->ts = L.ts;
+    P->ntiles = L.ntiles;
+    P->ksplit = L.ksplit;
+    P->kchunk = L.kchunk;
+    P->nslices = L.nslices;
+    P->flags = reinterpret_cast<unsigned*>(w + L.off_flags);
+    P->tile_cnt = reinterpret_cast<unsigned*>(w + L.off_tilecnt);
+    P->G[0] = reinterpret_cast<float*>(w + L.off_G0);
+    P->G[1] = reinterpret_cast<float*>(w + L.off_G1);
+    P->Gpart = reinterpret_cast<float*>(w + L.off_Gpart);
+    P->rp[0] = reinterpret_cast<float*>(w + L.off_rp0);
+    P->rp[1] = reinterpret_cast<float*>(w + L.off_rp1);
+    P->c = reinterpret_cast<float*>(w + L.off_c);
+}
+
+// ----------------------------------------------------------- validation
+
+static casgd_status check_bs(int32_t b, int32_t s) {
+    if (b < 1 || s < 1) {
+        set_error("b and s must be >= 1 (got b=%d, s=%d)", b, s);
+        return CASGD_EINVAL;
+    }
+    if ((int64_t)b * s > 4096) {
+        set_error("s*b = %lld exceeds the supported maximum 4096", (long long)b * s);
+        return CASGD_EUNSUPPORTED;
+    }
+    return CASGD_OK;
+}
+
+static casgd_status check_dense(const casgd_matrix* X) {
+    if (!X) {
+        set_error("X is NULL");
+        return CASGD_EINVAL;
+    }
+    if (X->layout != CASGD_DENSE) {
+        set_error("this entry point needs a dense X (layout %d)", X->layout);
+        return CASGD_EUNSUPPORTED;
+    }
+    if (X->m < 1 || X->n < 1 || X->ld < X->n) {
+        set_error("bad shape m=%lld n=%lld ld=%lld", (long long)X->m, (long long)X->n,
+                  (long long)X->ld);
+        return CASGD_EINVAL;
+    }
+    if (X->m > (1ll << 40) || X->n > (1ll << 31)) {
+        set_error("shape m=%lld n=%lld too large", (long long)X->m, (long long)X->n);
+        return CASGD_EUNSUPPORTED;
+    }
+    const int eb = dtype_bytes(X->dtype);
+    if (!eb) {
+        set_error("unknown dtype %d", X->dtype);
+        return CASGD_EINVAL;
+    }
+    if (!X->values) {
+        set_error("X->values is NULL");
+        return CASGD_EINVAL;
+    }
+    if ((reinterpret_cast<uintptr_t>(X->values) & 15) || ((X->ld * eb) & 15)) {
+        set_error("X must be 16-byte aligned with ld*elementsize a multiple of 16");
+        return CASGD_EINVAL;
+    }
+    if (X->dtype == CASGD_FP8E4M3 && !X->row_scale) {
+        set_error("FP8-E4M3 storage needs row_scale");
+        return CASGD_EINVAL;
+    }
+    return CASGD_OK;
+}
+
+static casgd_status check_csr(const casgd_matrix* X) {
+    if (!X || X->layout != CASGD_CSR) {
+        set_error("expected a CSR matrix");
+        return CASGD_EINVAL;
+    }
+    if (X->m < 1 || X->n < 1 || X->nnz < 0 || !X->row_ptr || (X->nnz > 0 && (!X->col_idx || !X->values))) {
+        set_error("bad CSR matrix (m=%lld n=%lld nnz=%lld)", (long long)X->m, (long long)X->n,
+                  (long long)X->nnz);
+        return CASGD_EINVAL;
+    }
+    if (X->dtype != CASGD_F32) {
+        set_error("CSR values must be FP32");
+        return CASGD_EUNSUPPORTED;
+    }
+    if (X->n > (1ll << 31) - 1) {
+        set_error("CSR column count too large");
+        return CASGD_EUNSUPPORTED;
+    }
+    return CASGD_OK;
+}
+
+static casgd_status check_scalars(double eta, double lambda) {
+    if (!(eta > 0) || !std::isfinite(eta) || !(lambda >= 0) || !std::isfinite(lambda)) {
+        set_error("need eta > 0 and lambda >= 0, both finite (eta=%g, lambda=%g)", eta, lambda);
+        return CASGD_EINVAL;
+    }
+    return CASGD_OK;
+}
+
+static casgd_status check_ws(const void* ws, size_t ws_bytes, size_t need) {
+    if (!ws) {
+        set_error("workspace is NULL");
+        return CASGD_EINVAL;
+    }
+    if (reinterpret_cast<uintptr_t>(ws) & 255) {
+        set_error("workspace must be 256-byte aligned");
+        return CASGD_EINVAL;
+    }
+    if (ws_bytes < need) {
+        set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
+        return CASGD_ENOMEM;
+    }
+    return CASGD_OK;
+}
+
+// Fill a Dense view for X, y, x and the scalars, bound to workspace ws.
+static casgd_status make_dense(const casgd_matrix* X, const float* y, float* x, double eta,
+                               double lambda, int32_t b, int32_t s, uint64_t seed,
+                               const casgd_opts* o, void* ws, size_t ws_bytes, Dense* P,
+                               DenseLayout* L, bool need_ws) {
+    casgd_status rc;
+    if ((rc = check_dense(X)) != CASGD_OK) return rc;
+    if ((rc = check_bs(b, s)) != CASGD_OK) return rc;
+    if ((rc = check_scalars(eta, lambda)) != CASGD_OK) return rc;
+    dense_layout(X->n, X->dtype, b, s, L);
+    if (need_ws && (rc = check_ws(ws, ws_bytes, L->total)) != CASGD_OK) return rc;
+    std::memset(P, 0, sizeof *P);
+    P->X = X->values;
+    P->scale = X->row_scale;
+    P->y = y;
+    P->x = x;
+    P->m = X->m;
+    P->n = X->n;
+    P->ld = X->ld;
+    P->b = b;
+    P->s = s;
+    P->seed = seed;
+    P->alpha_d = eta / b;
+    P->beta_d = 1.0 - eta * lambda;
+    P->alpha = (float)P->alpha_d;
+    P->beta = (float)P->beta_d;
+    P->beta_s = (float)std::pow(P->beta_d, (double)s);
+    if (need_ws) {
+        dense_bind(*L, ws, P);
+    } else {
+        P->sb = L->sb;
+        P->ts = L->ts;
+        P->ntiles = L->ntiles;
+        P->ksplit = L->ksplit;
+        P->kchunk = L->kchunk;
+        P->nslices = L->nslices;
+    }
+    if (o && o->snapshot_every > 0) {
+        if (!o->x_history) {
+            set_error("snapshot_every > 0 needs x_history");
+            return CASGD_EINVAL;
+        }
+        P->snap_every = o->snapshot_every;
+        P->x_hist = o->x_history;
+        P->t_hist = o->t_history;
+    }
+    return CASGD_OK;
+}
+
+}  // namespace casgd
+
+using namespace casgd;
+
+extern "C" {
+
+const char* casgd_status_string(casgd_status st) {
+    switch (st) {
+        case CASGD_OK: return "ok";
+        case CASGD_EINVAL: return "invalid argument";
+        case CASGD_EUNSUPPORTED: return "unsupported";
+        case CASGD_ENOMEM: return "workspace too small";
+        case CASGD_EDEVICE: return "HIP runtime error";
+        case CASGD_ENONFINITE: return "non-finite value";
+        case CASGD_ETIMEOUT: return "grid barrier timeout";
+        default: return "unknown status";
+    }
+}
+
+const char* casgd_last_error(void) { return t_err.c_str(); }
+
+int32_t casgd_version(void) { return 100; }
+
+casgd_status casgd_workspace_size(const casgd_matrix* X, int32_t b, int32_t s, size_t* bytes) {
+    casgd_status rc;
+    if (!bytes) {
+        set_error("bytes is NULL");
+        return CASGD_EINVAL;
+    }
+    if (X && X->layout == CASGD_CSR) return sparse_workspace_size(X, b, s, 1, bytes);
+    if ((rc = check_dense(X)) != CASGD_OK) return rc;
+    if ((rc = check_bs(b, s)) != CASGD_OK) return rc;
+    DenseLayout L;
+    dense_layout(X->n, X->dtype, b, s, &L);
+    *bytes = L.total;
+    return CASGD_OK;
+}
+
+casgd_status casgd_reset(void* ws, size_t ws_bytes, void* stream) {
+    casgd_status rc;
+    if ((rc = check_ws(ws, ws_bytes, FLAG_WORDS * 4)) != CASGD_OK) return rc;
+    return run_zero(static_cast<unsigned*>(ws), FLAG_WORDS, (hipStream_t)stream);
+}
+
+casgd_status casgd_check(const void* ws, size_t ws_bytes, void* stream) {
+    casgd_status rc;
+    if ((rc = check_ws(ws, ws_bytes, FLAG_WORDS * 4)) != CASGD_OK) return rc;
+    CASGD_HIP(hipStreamSynchronize((hipStream_t)stream));
+    unsigned f[2] = {0, 0};
+    CASGD_HIP(hipMemcpy(f, ws, sizeof f, hipMemcpyDeviceToHost));
+    if (f[FLAG_TIMEOUT]) {
+        set_error("a grid barrier of the fused kernel exceeded its spin limit");
+        return CASGD_ETIMEOUT;
+    }
+    if (f[FLAG_NONFINITE]) {
+        set_error("a margin, residual or weight became NaN or Inf");
+        return CASGD_ENONFINITE;
+    }
+    return CASGD_OK;
+}
+
+casgd_status casgd_fit(const casgd_matrix* X, const float* y, float* x, double eta,
+                       double lambda, int32_t b, int32_t s, uint64_t seed, uint64_t outer_begin,
+                       int64_t n_outer, const casgd_opts* opts, void* ws, size_t ws_bytes,
+                       void* stream) {
+    if (X && X->layout == CASGD_CSR)
+        return sparse_fit(X, y, x, &lambda, 1, eta, b, s, seed, outer_begin, n_outer, opts, ws,
+                          ws_bytes, stream);
+    if (!y || !x) {
+        set_error("y and x must not be NULL");
+        return CASGD_EINVAL;
+    }
+    if (n_outer < 0) {
+        set_error("n_outer must be >= 0");
+        return CASGD_EINVAL;
+    }
+    Dense P;
+    DenseLayout L;
+    casgd_status rc =
+        make_dense(X, y, x, eta, lambda, b, s, seed, opts, ws, ws_bytes, &P, &L, true);
+    if (rc != CASGD_OK) return rc;
+    FitPlan plan;
+    if ((rc = plan_fit(P, X->dtype, opts, n_outer, &plan)) != CASGD_OK) return rc;
+    return run_fit(P, X->dtype, outer_begin, n_outer, plan, (hipStream_t)stream);
+}
+
+casgd_status casgd_step(const casgd_matrix* X, const float* y, float* x, double eta,
+                        double lambda, int32_t b, int32_t s, uint64_t seed, uint64_t outer_iter,
+                        const casgd_opts* opts, void* ws, size_t ws_bytes, void* stream) {
+    return casgd_fit(X, y, x, eta, lambda, b, s, seed, outer_iter, 1, opts, ws, ws_bytes, stream);
+}
+
+casgd_status casgd_sample_indices(uint64_t seed, uint64_t t0, int64_t count, int64_t m,
+                                  int64_t* out, void* stream) {
+    if (count < 0 || m < 1 || (count > 0 && !out)) {
+        set_error("bad arguments (count=%lld, m=%lld)", (long long)count, (long long)m);
+        return CASGD_EINVAL;
+    }
+    return run_sample(seed, t0, count, m, out, (hipStream_t)stream);
+}
+
+casgd_status casgd_gram_margin(const casgd_matrix* X, const float* x, int32_t b, int32_t s,
+                               uint64_t seed, uint64_t outer_iter, float* G, float* r, void* ws,
+                               size_t ws_bytes, void* stream) {
+    if (!x || !G || !r) {
+        set_error("x, G and r must not be NULL");
+        return CASGD_EINVAL;
+    }
+    Dense P;
+    DenseLayout L;
+    casgd_status rc = make_dense(X, nullptr, const_cast<float*>(x), 1.0, 0.0, b, s, seed, nullptr,
+                                 ws, ws_bytes, &P, &L, true);
+    if (rc != CASGD_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = run_zero(P.tile_cnt, P.ntiles, st)) != CASGD_OK) return rc;
+    if ((rc = run_gram(P, X->dtype, G, outer_iter, st)) != CASGD_OK) return rc;
+    if ((rc = run_margin(P, X->dtype, outer_iter, P.rp[0], st)) != CASGD_OK) return rc;
+    return run_margin_reduce(P, P.rp[0], outer_iter, r, st);
+}
+
+casgd_status casgd_recurrence(const float* G, const float* r, const float* yI, int32_t b,
+                              int32_t s, double eta, double lambda, int32_t prec, float* c,
+                              float* delta, void* stream) {
+    casgd_status rc;
+    if ((s > 1 && !G) || !r || !yI || !c) {
+        set_error("G, r, yI and c must not be NULL");
+        return CASGD_EINVAL;
+    }
+    if ((rc = check_bs(b, s)) != CASGD_OK) return rc;
+    if ((rc = check_scalars(eta, lambda)) != CASGD_OK) return rc;
+    if (prec != 0 && prec != 32 && prec != 64) {
+        set_error("prec must be 0, 32 or 64");
+        return CASGD_EINVAL;
+    }
+    Dense P;
+    std::memset(&P, 0, sizeof P);
+    P.b = b;
+    P.s = s;
+    P.sb = b * s;
+    P.alpha_d = eta / b;
+    P.beta_d = 1.0 - eta * lambda;
+    P.alpha = (float)P.alpha_d;
+    P.beta = (float)P.beta_d;
+    P.m = 1;
+    const bool fp64 = prec == 64 || (prec == 0 && P.sb >= 512);
+    return run_recurrence(P, G, nullptr, 0, r, yI, c, delta, fp64, (hipStream_t)stream);
+}
+
+casgd_status casgd_update(const casgd_matrix* X, float* x, const float* c, int32_t b, int32_t s,
+                          uint64_t seed, uint64_t outer_iter, double eta, double lambda,
+                          void* stream) {
+    if (!x || !c) {
+        set_error("x and c must not be NULL");
+        return CASGD_EINVAL;
+    }
+    Dense P;
+    DenseLayout L;
+    casgd_status rc =
+        make_dense(X, nullptr, x, eta, lambda, b, s, seed, nullptr, nullptr, 0, &P, &L, false);
+    if (rc != CASGD_OK) return rc;
+    return run_update(P, X->dtype, c, outer_iter, (hipStream_t)stream);
+}
+
+casgd_status casgd_quantize(const float* src, int64_t m, int64_t n, int64_t ld_src, int32_t dtype,
+                            void* dst, int64_t ld_dst, float* row_scale, void* stream) {
+    const int eb = dtype_bytes(dtype);
+    if (!src || !dst || m < 1 || n < 1 || ld_src < n || ld_dst < n || !eb) {
+        set_error("bad arguments to casgd_quantize");
+        return CASGD_EINVAL;
+    }
+    if (dtype == CASGD_FP8E4M3 && !row_scale) {
+        set_error("FP8-E4M3 needs row_scale");
+        return CASGD_EINVAL;
+    }
+    return run_quantize(src, m, n, ld_src, dtype, dst, ld_dst, row_scale, (hipStream_t)stream);
+}
+
+size_t casgd_logloss_workspace_size(int64_t count) {
+    return count > 0 ? (size_t)count * kLossBlocks * sizeof(double) : 0;
+}
+
+casgd_status casgd_logloss(const casgd_matrix* X, const float* y, const float* xs, int64_t count,
+                           int64_t x_stride, double* out, void* ws, size_t ws_bytes,
+                           void* stream) {
+    if (!X || !y || !xs || !out || count < 1 || x_stride < X->n) {
+        set_error("bad arguments to casgd_logloss");
+        return CASGD_EINVAL;
+    }
+    casgd_status rc;
+    if (X->layout == CASGD_DENSE && (rc = check_dense(X)) != CASGD_OK) return rc;
+    if (X->layout == CASGD_CSR && (rc = check_csr(X)) != CASGD_OK) return rc;
+    if ((rc = check_ws(ws, ws_bytes, casgd_logloss_workspace_size(count))) != CASGD_OK) return rc;
+    return run_logloss(X, y, xs, count, x_stride, out, static_cast<double*>(ws),
+                       (hipStream_t)stream);
+}
+
+size_t casgd_colstats_workspace_size(const casgd_matrix* X) {
+    if (!X || X->n < 1) return 0;
+    return (size_t)kStatRowBlocks * X->n * 4 * sizeof(double);
+}
+
+casgd_status casgd_colstats(const casgd_matrix* X, float* stats, void* ws, size_t ws_bytes,
+                            void* stream) {
+    if (!X || !stats) {
+        set_error("X and stats must not be NULL");
+        return CASGD_EINVAL;
+    }
+    casgd_status rc;
+    if (X->layout == CASGD_DENSE && (rc = check_dense(X)) != CASGD_OK) return rc;
+    if (X->layout == CASGD_CSR && (rc = check_csr(X)) != CASGD_OK) return rc;
+    if ((rc = check_ws(ws, ws_bytes, casgd_colstats_workspace_size(X))) != CASGD_OK) return rc;
+    return run_colstats(X, stats, static_cast<double*>(ws), (hipStream_t)stream);
+}
+
+}  // extern "C"

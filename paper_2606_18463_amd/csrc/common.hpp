@@ -1,0 +1,219 @@
+// Device-side building blocks shared by the libcasgd kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace casgd {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- sampling
+// Counter-based SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): output t of
+// the stream that starts in state `seed` is mix(seed + (t+1) * golden gamma).
+// A sample is mapped to a row by the high half of the 128-bit product with m.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t t) {
+    uint64_t z = seed + (t + 1ull) * 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ int64_t sample_row(uint64_t seed, uint64_t t, uint64_t m) {
+    return (int64_t)__umul64hi(splitmix64(seed, t), m);
+}
+
+// ----------------------------------------------------------- storage types
+enum : int { DT_F32 = 0, DT_BF16 = 1, DT_F16 = 2, DT_FP8 = 3 };
+
+template <int DT> struct Store;
+template <> struct Store<DT_F32> { using T = float;    static constexpr int kVec = 4;  };
+template <> struct Store<DT_BF16> { using T = uint16_t; static constexpr int kVec = 8;  };
+template <> struct Store<DT_F16> { using T = uint16_t; static constexpr int kVec = 8;  };
+template <> struct Store<DT_FP8> { using T = uint8_t;  static constexpr int kVec = 16; };
+
+// OCP E4M3: sign, 4 exponent bits (bias 7), 3 mantissa bits; exponent field 0
+// is subnormal (m * 2^-9). Code 0x7f/0xff is NaN and never produced here.
+__device__ __forceinline__ float e4m3_to_float(uint32_t c) {
+    const uint32_t e = (c >> 3) & 15u, mnt = c & 7u;
+    float v = (e == 0) ? (float)mnt * 0.001953125f
+                       : __uint_as_float(((e + 120u) << 23) | (mnt << 20));
+    return (c & 0x80u) ? -v : v;
+}
+
+// Round to nearest, ties to even, saturating to +-448.
+__device__ __forceinline__ uint32_t float_to_e4m3(float v) {
+    const uint32_t sign = (__float_as_uint(v) >> 24) & 0x80u;
+    const float a = fabsf(v);
+    if (!(a < 448.0f)) return sign | 0x7eu;            // >= 448 (and NaN) -> 448
+    if (a < 0.015625f) {                               // below 2^-6: subnormal grid 2^-9
+        const float q = rintf(a * 512.0f);             // exact scaling, RNE
+        return sign | (uint32_t)q;                     // q == 8 is the smallest normal
+    }
+    const uint32_t bits = __float_as_uint(a);
+    int e = (int)(bits >> 23) - 127;
+    const uint32_t mant = bits & 0x7fffffu;
+    uint32_t q = mant >> 20;
+    const uint32_t rem = mant & 0xfffffu;
+    if (rem > 0x80000u || (rem == 0x80000u && (q & 1u))) ++q;
+    if (q == 8u) { q = 0u; ++e; }
+    const int ef = e + 7;
+    if (ef > 15 || (ef == 15 && q == 7u)) return sign | 0x7eu;
+    return sign | ((uint32_t)ef << 3) | q;
+}
+
+__device__ __forceinline__ float bf16_to_float(uint32_t h) { return __uint_as_float(h << 16); }
+
+__device__ __forceinline__ uint32_t float_to_bf16(float v) {
+    const uint32_t u = __float_as_uint(v);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+__device__ __forceinline__ float f16_to_float(uint32_t h) {
+    _Float16 x;
+    uint16_t hb = (uint16_t)h;
+    __builtin_memcpy(&x, &hb, 2);
+    return (float)x;
+}
+
+__device__ __forceinline__ uint32_t float_to_f16(float v) {
+    _Float16 x = (_Float16)v;
+    uint16_t hb;
+    __builtin_memcpy(&hb, &x, 2);
+    return hb;
+}
+
+// A 16-byte vector of stored elements and its conversion to FP32.
+struct V16 { uint32_t w[4]; };
+
+template <int DT>
+__device__ __forceinline__ float v16_elem(const V16& v, int e) {
+    if constexpr (DT == DT_F32) {
+        return __uint_as_float(v.w[e]);
+    } else if constexpr (DT == DT_BF16) {
+        const uint32_t w = v.w[e >> 1];
+        return (e & 1) ? __uint_as_float(w & 0xffff0000u) : __uint_as_float(w << 16);
+    } else if constexpr (DT == DT_F16) {
+        const uint32_t w = v.w[e >> 1];
+        return f16_to_float((e & 1) ? (w >> 16) : (w & 0xffffu));
+    } else {
+        return e4m3_to_float((v.w[e >> 2] >> (8 * (e & 3))) & 0xffu);
+    }
+}
+
+// Load kVec elements starting at element k of a row with n valid elements.
+// Full vectors use one 16-byte load; a vector crossing n is read element-wise
+// and padded with zeros; a vector starting at or beyond n is all zeros.
+template <int DT>
+__device__ __forceinline__ V16 load_v16(const typename Store<DT>::T* row, int64_t k, int64_t n) {
+    constexpr int VEC = Store<DT>::kVec;
+    V16 v;
+    if (k + VEC <= n) {
+        const uint4 u = *reinterpret_cast<const uint4*>(row + k);
+        v.w[0] = u.x; v.w[1] = u.y; v.w[2] = u.z; v.w[3] = u.w;
+        return v;
+    }
+    v.w[0] = v.w[1] = v.w[2] = v.w[3] = 0u;
+    if (k >= n) return v;
+    constexpr int BYTES = 16 / VEC;
+    for (int e = 0; e < VEC; ++e) {
+        if (k + e < n) {
+            uint32_t bits;
+            if constexpr (BYTES == 4) bits = reinterpret_cast<const uint32_t*>(row)[k + e];
+            else if constexpr (BYTES == 2) bits = reinterpret_cast<const uint16_t*>(row)[k + e];
+            else bits = reinterpret_cast<const uint8_t*>(row)[k + e];
+            v.w[(e * BYTES) >> 2] |= bits << (8 * ((e * BYTES) & 3));
+        }
+    }
+    return v;
+}
+
+// ------------------------------------------------------- wave reductions
+template <typename T>
+__device__ __forceinline__ T shfl_xor(T v, int mask) {
+    return __shfl_xor(v, mask, kWave);
+}
+
+// Sum over groups of `G` consecutive lanes (G a power of two <= 64); every lane
+// of the group receives the total.
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) v += shfl_xor(v, off);
+    return v;
+}
+
+// ------------------------------------------------- device-scope atomics
+__device__ __forceinline__ unsigned atomic_add_acq_rel(unsigned* p, unsigned v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned atomic_load_acquire(unsigned* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned atomic_load_relaxed(unsigned* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void atomic_store_release(unsigned* p, unsigned v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void atomic_store_relaxed(unsigned* p, unsigned v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Flag words at the start of every workspace.
+enum : int {
+    FLAG_NONFINITE = 0,   // set when a margin, residual or weight is NaN/Inf
+    FLAG_TIMEOUT = 1,     // set when a grid barrier exceeded its spin limit
+    FLAG_BAR_COUNT = 16,  // grid barrier arrival counter (own 64-byte line)
+    FLAG_BAR_GEN = 32,    // grid barrier generation (own 64-byte line)
+    FLAG_WORDS = 64
+};
+
+// Entry points without a workspace pass flags == nullptr and report nothing.
+__device__ __forceinline__ void raise_flag(unsigned* flags, int which) {
+    if (flags) __hip_atomic_fetch_or(&flags[which], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid-wide barrier for a launch whose workgroups are all resident (the
+// cooperative launch guarantees it). Sense is kept in a generation counter.
+// The wait is bounded: after `spin_limit` polls the timeout flag is raised
+// and every workgroup leaves the barrier (and then the kernel) at once, so a
+// launch can never wait forever. Returns false when the kernel must stop.
+__device__ __forceinline__ bool grid_barrier(unsigned* flags, unsigned nblocks,
+                                             unsigned long long spin_limit) {
+    __shared__ int s_stop;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned* count = flags + FLAG_BAR_COUNT;
+        unsigned* gen = flags + FLAG_BAR_GEN;
+        const unsigned g = atomic_load_relaxed(gen);
+        const unsigned arrived = atomic_add_acq_rel(count, 1u);
+        int stop = 0;
+        if (arrived == nblocks - 1) {
+            atomic_store_relaxed(count, 0u);
+            atomic_store_release(gen, g + 1u);
+        } else {
+            unsigned long long spins = 0;
+            while (atomic_load_acquire(gen) == g) {
+                if (++spins > spin_limit) {
+                    raise_flag(flags, FLAG_TIMEOUT);
+                    stop = 1;
+                    break;
+                }
+                if ((spins & 255ull) == 0 && atomic_load_relaxed(flags + FLAG_TIMEOUT)) {
+                    stop = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        if (atomic_load_relaxed(flags + FLAG_TIMEOUT)) stop = 1;
+        s_stop = stop;
+    }
+    __syncthreads();
+    __threadfence();
+    return s_stop == 0;
+}
+
+}  // namespace casgd

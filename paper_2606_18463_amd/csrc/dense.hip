@@ -1,0 +1,386 @@
+// Kernels and launchers of the dense s-step SGD path.
+//
+// Two execution forms share the device functions of dense.hpp:
+//  * one launch per phase (gram, recurrence, update+next margin), stream
+//    ordered; kernel boundaries are the synchronisation points;
+//  * one persistent cooperative launch for a whole fit, with grid barriers.
+//    Variant 1 ("redundant"): every workgroup that owns update slices runs
+//    the recurrence itself, so an outer iteration needs one barrier; this
+//    suits small s*b (plain SGD at s = 1 is this variant). Variant 2
+//    ("single"): workgroup 0 runs the recurrence while all others compute
+//    the next outer iteration's Gram tiles (which do not depend on x), then
+//    everyone applies the update; two barriers per outer iteration.
+#include <algorithm>
+#include <cstring>
+
+#include "internal.hpp"
+
+namespace casgd {
+
+// ------------------------------------------------------------------ kernels
+
+__global__ void k_zero_u32(unsigned* p, int64_t words) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < words) p[i] = 0u;
+}
+
+template <int DT>
+__global__ __launch_bounds__(kNT) void k_gram(Dense P, float* Gout, uint64_t h, int nitems) {
+    const int item = blockIdx.x * kNW + (threadIdx.x >> 6);
+    if (item >= nitems) return;
+    gram_item<DT>(P, Gout, h, item);
+}
+
+template <int DT>
+__global__ __launch_bounds__(kNT) void k_update(Dense P, const float* c, uint64_t h, int do_update,
+                                                uint64_t hn, int do_margin, float* rp_out,
+                                                int64_t snap_row) {
+    constexpr int KW = slice_width<DT>();
+    __shared__ float red[kNW * KW];
+    __shared__ float xs[KW];
+    update_margin_slice<DT, kNW>(P, blockIdx.x, c, h, do_update != 0, hn, do_margin != 0, rp_out,
+                                 red, xs, snap_row);
+}
+
+__global__ __launch_bounds__(kNT) void k_margin_reduce(Dense P, const float* rp, uint64_t h,
+                                                       float* r_out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= P.sb) return;
+    float r = 0.f;
+    for (int sl = 0; sl < P.nslices; ++sl) r += rp[(int64_t)sl * P.sb + t];
+    if (P.scale) r *= P.scale[sample_row(P.seed, h * (uint64_t)P.sb + t, P.m)];
+    r_out[t] = r;
+}
+
+template <typename ACC>
+__global__ __launch_bounds__(kNT) void k_recurrence(Dense P, const float* G, const float* rp,
+                                                    uint64_t h, const float* r_in,
+                                                    const float* y_in, float* c,
+                                                    float* delta_out, int tpr) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    ACC* dl = reinterpret_cast<ACC*>(lds);
+    ACC* pw = dl + P.sb;
+    recurrence<ACC, kNT>(P, G, rp, h, r_in, y_in, c, delta_out, dl, pw, tpr);
+}
+
+// LDS bytes of the persistent kernel: recurrence history, decay powers, the
+// workgroup's copy of c (variant 1), and the update's reduction buffers.
+__host__ __device__ inline size_t fit_lds_bytes(int sb, int s, int acc_bytes, int kw) {
+    size_t off = (size_t)sb * acc_bytes;
+    off += (size_t)(s + 1) * acc_bytes;
+    off = (off + 15) & ~(size_t)15;
+    off += (size_t)sb * 4;                // c copy
+    off += (size_t)kNW * kw * 4 + kw * 4; // red + xs
+    return off;
+}
+
+template <int DT, typename ACC, int VARIANT>
+__global__ __launch_bounds__(kNT) void k_fit(Dense P, uint64_t h0, int64_t H,
+                                             unsigned long long spin, int tpr) {
+    constexpr int KW = slice_width<DT>();
+    extern __shared__ __align__(16) unsigned char lds[];
+    ACC* dl = reinterpret_cast<ACC*>(lds);
+    ACC* pw = dl + P.sb;
+    size_t off = (size_t)P.sb * sizeof(ACC) + (size_t)(P.s + 1) * sizeof(ACC);
+    off = (off + 15) & ~(size_t)15;
+    float* cl = reinterpret_cast<float*>(lds + off);
+    float* red = cl + P.sb;
+    float* xs = red + kNW * KW;
+
+    const int nb = gridDim.x;
+    const int wg = blockIdx.x;
+    const int wave = threadIdx.x >> 6;
+    const int nitems = P.ntiles * P.ksplit;
+    const bool has_gram = P.s > 1;
+
+    if (threadIdx.x == 0 && wg == 0 && P.t_hist) P.t_hist[0] = (int64_t)wall_clock64();
+
+    // Prologue: Gram of h0 and the margins of h0 from the incoming x.
+    if (has_gram) {
+        const int first = (VARIANT == 2) ? 1 : 0;
+        const int nw = (nb - first) * kNW;
+        if (wg >= first)
+            for (int it = (wg - first) * kNW + wave; it < nitems; it += nw)
+                gram_item<DT>(P, P.G[0], h0, it);
+    }
+    for (int sl = wg; sl < P.nslices; sl += nb)
+        update_margin_slice<DT, kNW>(P, sl, nullptr, 0, false, h0, true, P.rp[0], red, xs, -1);
+    if (!grid_barrier(P.flags, nb, spin)) return;
+
+    for (int64_t hh = 0; hh < H; ++hh) {
+        const uint64_t h = h0 + (uint64_t)hh;
+        const int cur = (int)(hh & 1), nxt = cur ^ 1;
+        const bool more = hh + 1 < H;
+        const bool snap = P.snap_every > 0 && ((hh + 1) % P.snap_every) == 0;
+        const int64_t snap_row = snap ? (hh + 1) / P.snap_every - 1 : -1;
+        if (VARIANT == 1) {
+            if (wg < P.nslices) {
+                recurrence<ACC, kNT>(P, P.G[cur], P.rp[cur], h, nullptr, nullptr, cl, nullptr, dl,
+                                     pw, tpr);
+                for (int sl = wg; sl < P.nslices; sl += nb)
+                    update_margin_slice<DT, kNW>(P, sl, cl, h, true, h + 1, more, P.rp[nxt], red,
+                                                 xs, snap_row);
+            }
+            if (has_gram && more)
+                for (int it = wg * kNW + wave; it < nitems; it += nb * kNW)
+                    gram_item<DT>(P, P.G[nxt], h + 1, it);
+            if (!grid_barrier(P.flags, nb, spin)) return;
+        } else {
+            if (wg == 0) {
+                recurrence<ACC, kNT>(P, P.G[cur], P.rp[cur], h, nullptr, nullptr, P.c, nullptr, dl,
+                                     pw, tpr);
+            } else if (has_gram && more) {
+                for (int it = (wg - 1) * kNW + wave; it < nitems; it += (nb - 1) * kNW)
+                    gram_item<DT>(P, P.G[nxt], h + 1, it);
+            }
+            if (!grid_barrier(P.flags, nb, spin)) return;
+            for (int sl = wg; sl < P.nslices; sl += nb)
+                update_margin_slice<DT, kNW>(P, sl, P.c, h, true, h + 1, more, P.rp[nxt], red, xs,
+                                             snap_row);
+            if (!grid_barrier(P.flags, nb, spin)) return;
+        }
+        if (snap && wg == 0 && threadIdx.x == 0 && P.t_hist)
+            P.t_hist[snap_row + 1] = (int64_t)wall_clock64();
+    }
+}
+
+// ------------------------------------------------------------------ host
+
+namespace {
+
+template <int DT>
+casgd_status launch_gram_t(const Dense& P, float* Gout, uint64_t h, hipStream_t st) {
+    const int nitems = P.ntiles * P.ksplit;
+    if (nitems == 0 || P.s < 2) return CASGD_OK;
+    const int grid = (nitems + kNW - 1) / kNW;
+    hipLaunchKernelGGL(k_gram<DT>, dim3(grid), dim3(kNT), 0, st, P, Gout, h, nitems);
+    CASGD_HIP(hipGetLastError());
+    return CASGD_OK;
+}
+
+template <int DT>
+casgd_status launch_update_t(const Dense& P, const float* c, uint64_t h, int do_update,
+                             uint64_t hn, int do_margin, float* rp_out, int64_t snap_row,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_update<DT>, dim3(P.nslices), dim3(kNT), 0, st, P, c, h, do_update, hn,
+                       do_margin, rp_out, snap_row);
+    CASGD_HIP(hipGetLastError());
+    return CASGD_OK;
+}
+
+template <typename ACC>
+size_t rec_lds(const Dense& P) {
+    return (size_t)P.sb * sizeof(ACC) + (size_t)(P.s + 1) * sizeof(ACC);
+}
+
+template <int DT, typename ACC, int V>
+casgd_status launch_fit_t(const Dense& P, uint64_t h0, int64_t H, const FitPlan& plan,
+                          hipStream_t st) {
+    const size_t lds = fit_lds_bytes(P.sb, P.s, (int)sizeof(ACC), slice_width<DT>());
+    auto kern = k_fit<DT, ACC, V>;
+    if (lds > 65536) {
+        set_error("fused kernel needs %zu bytes of LDS (s*b too large for it)", lds);
+        return CASGD_EUNSUPPORTED;
+    }
+    Dense Pc = P;
+    uint64_t h0v = h0;
+    int64_t Hv = H;
+    unsigned long long spin = plan.spin;
+    int tpr = recurrence_tpr(kNT, P.b);
+    void* args[] = {&Pc, &h0v, &Hv, &spin, &tpr};
+    CASGD_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(plan.grid),
+                                         dim3(kNT), args, (unsigned)lds, st));
+    return CASGD_OK;
+}
+
+template <int DT, typename ACC, int V>
+int fit_max_grid(const Dense& P) {
+    const size_t lds = fit_lds_bytes(P.sb, P.s, (int)sizeof(ACC), slice_width<DT>());
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void*>(k_fit<DT, ACC, V>), kNT, lds) != hipSuccess)
+        return 0;
+    return per_cu * device_cus();
+}
+
+template <int DT>
+casgd_status dispatch_fit_dt(const Dense& P, uint64_t h0, int64_t H, const FitPlan& plan,
+                             hipStream_t st) {
+    if (plan.recur64) {
+        return plan.variant == 1 ? launch_fit_t<DT, double, 1>(P, h0, H, plan, st)
+                                 : launch_fit_t<DT, double, 2>(P, h0, H, plan, st);
+    }
+    return plan.variant == 1 ? launch_fit_t<DT, float, 1>(P, h0, H, plan, st)
+                             : launch_fit_t<DT, float, 2>(P, h0, H, plan, st);
+}
+
+template <int DT>
+int max_grid_dt(const Dense& P, int recur64, int variant) {
+    if (recur64)
+        return variant == 1 ? fit_max_grid<DT, double, 1>(P) : fit_max_grid<DT, double, 2>(P);
+    return variant == 1 ? fit_max_grid<DT, float, 1>(P) : fit_max_grid<DT, float, 2>(P);
+}
+
+int max_grid(const Dense& P, int dtype, int recur64, int variant) {
+    switch (dtype) {
+        case DT_F32: return max_grid_dt<DT_F32>(P, recur64, variant);
+        case DT_BF16: return max_grid_dt<DT_BF16>(P, recur64, variant);
+        case DT_F16: return max_grid_dt<DT_F16>(P, recur64, variant);
+        default: return max_grid_dt<DT_FP8>(P, recur64, variant);
+    }
+}
+
+}  // namespace
+
+casgd_status run_zero(unsigned* p, int64_t words, hipStream_t st) {
+    if (words <= 0) return CASGD_OK;
+    const int grid = (int)((words + 255) / 256);
+    hipLaunchKernelGGL(k_zero_u32, dim3(grid), dim3(256), 0, st, p, words);
+    CASGD_HIP(hipGetLastError());
+    return CASGD_OK;
+}
+
+casgd_status run_gram(const Dense& P, int dtype, float* Gout, uint64_t h, hipStream_t st) {
+    switch (dtype) {
+        case DT_F32: return launch_gram_t<DT_F32>(P, Gout, h, st);
+        case DT_BF16: return launch_gram_t<DT_BF16>(P, Gout, h, st);
+        case DT_F16: return launch_gram_t<DT_F16>(P, Gout, h, st);
+        default: return launch_gram_t<DT_FP8>(P, Gout, h, st);
+    }
+}
+
+static casgd_status run_update_margin(const Dense& P, int dtype, const float* c, uint64_t h,
+                                      int do_update, uint64_t hn, int do_margin, float* rp_out,
+                                      int64_t snap_row, hipStream_t st) {
+    switch (dtype) {
+        case DT_F32:
+            return launch_update_t<DT_F32>(P, c, h, do_update, hn, do_margin, rp_out, snap_row, st);
+        case DT_BF16:
+            return launch_update_t<DT_BF16>(P, c, h, do_update, hn, do_margin, rp_out, snap_row, st);
+        case DT_F16:
+            return launch_update_t<DT_F16>(P, c, h, do_update, hn, do_margin, rp_out, snap_row, st);
+        default:
+            return launch_update_t<DT_FP8>(P, c, h, do_update, hn, do_margin, rp_out, snap_row, st);
+    }
+}
+
+casgd_status run_margin(const Dense& P, int dtype, uint64_t h, float* rp_out, hipStream_t st) {
+    return run_update_margin(P, dtype, nullptr, 0, 0, h, 1, rp_out, -1, st);
+}
+
+casgd_status run_update(const Dense& P, int dtype, const float* c, uint64_t h, hipStream_t st) {
+    return run_update_margin(P, dtype, c, h, 1, 0, 0, nullptr, -1, st);
+}
+
+casgd_status run_margin_reduce(const Dense& P, const float* rp, uint64_t h, float* r_out,
+                               hipStream_t st) {
+    const int grid = (P.sb + kNT - 1) / kNT;
+    hipLaunchKernelGGL(k_margin_reduce, dim3(grid), dim3(kNT), 0, st, P, rp, h, r_out);
+    CASGD_HIP(hipGetLastError());
+    return CASGD_OK;
+}
+
+casgd_status run_recurrence(const Dense& P, const float* G, const float* rp, uint64_t h,
+                            const float* r_in, const float* y_in, float* c, float* delta_out,
+                            bool fp64, hipStream_t st) {
+    const int tpr = recurrence_tpr(kNT, P.b);
+    if (fp64) {
+        const size_t lds = rec_lds<double>(P);
+        if (lds > 65536) {
+            set_error("recurrence needs %zu bytes of LDS", lds);
+            return CASGD_EUNSUPPORTED;
+        }
+        hipLaunchKernelGGL(k_recurrence<double>, dim3(1), dim3(kNT), lds, st, P, G, rp, h, r_in,
+                           y_in, c, delta_out, tpr);
+    } else {
+        const size_t lds = rec_lds<float>(P);
+        hipLaunchKernelGGL(k_recurrence<float>, dim3(1), dim3(kNT), lds, st, P, G, rp, h, r_in,
+                           y_in, c, delta_out, tpr);
+    }
+    CASGD_HIP(hipGetLastError());
+    return CASGD_OK;
+}
+
+casgd_status plan_fit(const Dense& P, int dtype, const casgd_opts* o, int64_t H, FitPlan* plan) {
+    const int64_t sb = P.sb;
+    int prec = o ? o->recur_prec : 0;
+    if (prec != 0 && prec != 32 && prec != 64) {
+        set_error("recur_prec must be 0, 32 or 64 (got %d)", prec);
+        return CASGD_EINVAL;
+    }
+    plan->recur64 = prec == 64 || (prec == 0 && sb >= 512);
+    plan->exec_mode = (o && o->exec_mode) ? o->exec_mode : 1;
+    if (plan->exec_mode != 1 && plan->exec_mode != 2) {
+        set_error("exec_mode must be 0, 1 or 2 (got %d)", plan->exec_mode);
+        return CASGD_EINVAL;
+    }
+    plan->spin = (o && o->spin_limit > 0) ? (unsigned long long)o->spin_limit : (1ull << 24);
+    // Strict block-lower Gram bytes read by each recurrence.
+    const double gl_bytes = 4.0 * P.b * (double)P.b * P.s * (P.s - 1) / 2.0;
+    int variant = (o && o->fused_variant) ? o->fused_variant : (gl_bytes <= 256.0 * 1024 ? 1 : 2);
+    if (variant != 1 && variant != 2) {
+        set_error("fused_variant must be 0, 1 or 2 (got %d)", variant);
+        return CASGD_EINVAL;
+    }
+    plan->variant = variant;
+    plan->grid = 0;
+    if (plan->exec_mode == 2) return CASGD_OK;
+    const size_t lds = fit_lds_bytes(P.sb, P.s, plan->recur64 ? 8 : 4, slice_width_of(dtype));
+    if (lds > 65536) {
+        plan->exec_mode = 2;  // the fused kernel cannot hold this recurrence in LDS
+        return CASGD_OK;
+    }
+    const int maxg = max_grid(P, dtype, plan->recur64, variant);
+    if (maxg <= 0) {
+        plan->exec_mode = 2;
+        return CASGD_OK;
+    }
+    const int nitems = P.s > 1 ? P.ntiles * P.ksplit : 0;
+    int want = std::max(P.nslices, (nitems + kNW - 1) / kNW + (variant == 2 ? 1 : 0));
+    want = std::max(want, variant == 2 ? 2 : 1);
+    if (o && o->grid_blocks > 0) want = o->grid_blocks;
+    plan->grid = std::min(want, maxg);
+    if (variant == 2 && plan->grid < 2) plan->exec_mode = 2;
+    (void)H;
+    return CASGD_OK;
+}
+
+casgd_status run_fit(const Dense& P, int dtype, uint64_t h0, int64_t H, const FitPlan& plan,
+                     hipStream_t st) {
+    if (H <= 0) return CASGD_OK;
+    casgd_status rc;
+    // Split-K counters must start at zero (they reset themselves after use,
+    // but a launch that stopped early may leave them set).
+    if ((rc = run_zero(P.tile_cnt, P.ntiles, st)) != CASGD_OK) return rc;
+    if (plan.exec_mode == 1) {
+        // Barrier words start from zero for every fused launch.
+        if ((rc = run_zero(P.flags + FLAG_BAR_COUNT, FLAG_WORDS - FLAG_BAR_COUNT, st)) != CASGD_OK)
+            return rc;
+        switch (dtype) {
+            case DT_F32: return dispatch_fit_dt<DT_F32>(P, h0, H, plan, st);
+            case DT_BF16: return dispatch_fit_dt<DT_BF16>(P, h0, H, plan, st);
+            case DT_F16: return dispatch_fit_dt<DT_F16>(P, h0, H, plan, st);
+            default: return dispatch_fit_dt<DT_FP8>(P, h0, H, plan, st);
+        }
+    }
+    // Stream-ordered: margin(h0); then per outer: gram(h), recurrence(h),
+    // update(h) fused with margin(h+1).
+    if ((rc = run_update_margin(P, dtype, nullptr, 0, 0, h0, 1, P.rp[0], -1, st)) != CASGD_OK)
+        return rc;
+    for (int64_t hh = 0; hh < H; ++hh) {
+        const uint64_t h = h0 + (uint64_t)hh;
+        const bool more = hh + 1 < H;
+        const bool snap = P.snap_every > 0 && ((hh + 1) % P.snap_every) == 0;
+        const int64_t snap_row = snap ? (hh + 1) / P.snap_every - 1 : -1;
+        if ((rc = run_gram(P, dtype, P.G[0], h, st)) != CASGD_OK) return rc;
+        if ((rc = run_recurrence(P, P.G[0], P.rp[0], h, nullptr, nullptr, P.c, nullptr,
+                                 plan.recur64 != 0, st)) != CASGD_OK)
+            return rc;
+        if ((rc = run_update_margin(P, dtype, P.c, h, 1, h + 1, more ? 1 : 0, P.rp[0], snap_row,
+                                    st)) != CASGD_OK)
+            return rc;
+    }
+    return CASGD_OK;
+}
+
+}  // namespace casgd

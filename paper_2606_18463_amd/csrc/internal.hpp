@@ -1,0 +1,64 @@
+// Host-side internals of libcasgd shared between translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/casgd.h"
+#include "dense.hpp"
+
+namespace casgd {
+
+void set_error(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+casgd_status hip_fail(hipError_t e, const char* what);
+
+#define CASGD_HIP(call)                                   \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+int dtype_bytes(int dtype);
+int dtype_vec(int dtype);          // elements per 16-byte vector
+int slice_width_of(int dtype);     // columns per update / margin slice
+
+constexpr int kNT = 512;           // threads per workgroup of the dense kernels
+constexpr int kNW = kNT / 64;
+
+// Workspace layout of one dense problem (byte offsets, 256-byte aligned).
+struct DenseLayout {
+    int sb, ts, ntiles, needed, ksplit, nslices;
+    int64_t kchunk;
+    size_t off_flags, off_tilecnt, off_G0, off_G1, off_Gpart, off_rp0, off_rp1, off_c, off_r,
+        off_y, off_d, total;
+};
+
+bool dense_layout(int64_t n, int dtype, int b, int s, DenseLayout* L);
+void dense_bind(const DenseLayout& L, void* ws, Dense* P);
+
+// Tuning knobs chosen by the host (or the autotuner).
+struct FitPlan {
+    int exec_mode;      // 1 persistent, 2 stream-ordered
+    int variant;        // 1 redundant recurrence (one barrier/outer), 2 single recurrence group
+    int grid;           // persistent grid size
+    int recur64;        // FP64 recurrence
+    unsigned long long spin;
+};
+
+casgd_status plan_fit(const Dense& P, int dtype, const casgd_opts* o, int64_t H, FitPlan* plan);
+casgd_status run_fit(const Dense& P, int dtype, uint64_t h0, int64_t H, const FitPlan& plan,
+                     hipStream_t st);
+casgd_status run_gram(const Dense& P, int dtype, float* Gout, uint64_t h, hipStream_t st);
+casgd_status run_margin(const Dense& P, int dtype, uint64_t h, float* rp_out, hipStream_t st);
+casgd_status run_margin_reduce(const Dense& P, const float* rp, uint64_t h, float* r_out,
+                               hipStream_t st);
+casgd_status run_recurrence(const Dense& P, const float* G, const float* rp, uint64_t h,
+                            const float* r_in, const float* y_in, float* c, float* delta_out,
+                            bool fp64, hipStream_t st);
+casgd_status run_update(const Dense& P, int dtype, const float* c, uint64_t h, hipStream_t st);
+casgd_status run_zero(unsigned* p, int64_t words, hipStream_t st);
+
+int device_cus();
+
+}  // namespace casgd

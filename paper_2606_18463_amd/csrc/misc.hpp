@@ -1,0 +1,28 @@
+// Host launchers of the auxiliary kernels (sampling, storage conversion, loss,
+// column statistics) and of the sparse path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/casgd.h"
+
+namespace casgd {
+
+casgd_status run_sample(uint64_t seed, uint64_t t0, int64_t count, int64_t m, int64_t* out,
+                        hipStream_t st);
+casgd_status run_quantize(const float* src, int64_t m, int64_t n, int64_t ld_src, int dtype,
+                          void* dst, int64_t ld_dst, float* row_scale, hipStream_t st);
+constexpr int kLossBlocks = 256;     // partial sums per weight vector
+constexpr int kStatRowBlocks = 64;   // row blocks of the column statistics
+casgd_status run_logloss(const casgd_matrix* X, const float* y, const float* xs, int64_t count,
+                         int64_t x_stride, double* out, double* partial, hipStream_t st);
+casgd_status run_colstats(const casgd_matrix* X, float* stats, double* partial, hipStream_t st);
+
+casgd_status sparse_workspace_size(const casgd_matrix* X, int32_t b, int32_t s, int32_t lanes,
+                                   size_t* bytes);
+casgd_status sparse_fit(const casgd_matrix* X, const float* y, float* x_lanes,
+                        const double* lambdas_host, int32_t L, double eta, int32_t b, int32_t s,
+                        uint64_t seed, uint64_t outer_begin, int64_t n_outer,
+                        const casgd_opts* opts, void* ws, size_t ws_bytes, void* stream);
+
+}  // namespace casgd
