@@ -1,0 +1,274 @@
+#!/usr/bin/env python3
+"""Benchmark: SGD updates/s of s-step (communication-avoiding) SGD on one MI355X.
+
+Workload (the dense FP32 configuration): X is 2^20 x 2048 FP32 with N(0, 1/2048)
+entries and 205 seeded columns scaled x10, labels sign(Xw) with 5% flips,
+b = 64, lambda = 1e-5, seed 42. One "step" is one outer iteration of the
+method: sample s*b rows, Gram + margins, s residual corrections, one update
+(s SGD updates). `value` is SGD updates per second over the K timed steps of
+one fused launch (inputs already resident in HBM).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--s 16] [--dtype f32]
+
+Prints one JSON line. `--sweep` adds a per-s table; `--eta-sweep` runs the
+step-size selection (one epoch of plain SGD per candidate); `--no-cpu` skips
+the CPU-oracle baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+# Step size of the dense FP32 workload, chosen by the one-epoch plain-SGD sweep
+# over powers of two (bench.py --eta-sweep); reused for every s and precision.
+ETA_C2 = 2.0
+LAMBDA_C2 = 1e-5
+B_C2 = 64
+SEED = 42
+
+PEAK = {  # MI355X published dense peaks
+    "hbm_GBps": 8000.0,
+    "f32_TFLOPs": 157.3, "bf16_TFLOPs": 2500.0, "f16_TFLOPs": 2500.0, "fp8_TFLOPs": 5000.0,
+    "f64_TFLOPs": 78.6,
+}
+DT_NAME = {"f32": 0, "bf16": 1, "f16": 2, "fp8": 3}
+DT_BYTES = {"f32": 4, "bf16": 2, "f16": 2, "fp8": 1}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def outer_flops(b: int, s: int, n: int) -> float:
+    """Algorithmic flops of one outer iteration: strict block-lower Gram
+    s(s-1) b^2 n, margins 2 s b n, update 2 s b n, corrections b^2 s (s-1)."""
+    return s * (s - 1) * b * b * n + 4.0 * s * b * n + b * b * s * (s - 1)
+
+
+def outer_bytes(b: int, s: int, n: int, e: int) -> float:
+    """Algorithmic HBM bytes of one outer iteration: the sampled rows once,
+    x read and written, indices and labels."""
+    return s * b * n * e + 8.0 * n + 8.0 * s * b + (4.0 * s * b if e == 1 else 0.0)
+
+
+def gram_flops(b: int, s: int, n: int) -> float:
+    return s * (s - 1) * b * b * n
+
+
+def paper_ai(b: int, s: int, n: int, e: int) -> float:
+    """The paper's roofline arithmetic intensity convention (Fig. 5):
+    2 (sb)^2 n / (2 sb n e + 4 (sb)^2)."""
+    sb = s * b
+    return 2.0 * sb * sb * n / (2.0 * sb * n * e + 4.0 * sb * sb)
+
+
+class Workload:
+    def __init__(self, m: int, n: int, seed: int = SEED, with_test: bool = False):
+        from workloads import dense_c2
+        t = time.perf_counter()
+        self.p = dense_c2(seed, m=m, n=n, m_test=(m // 4 if with_test else 1))
+        log(f"[bench] generated X {m}x{n} fp32 in {time.perf_counter() - t:.1f}s")
+        self.m, self.n = m, n
+
+
+def upload(cg, wl: Workload, dtype: str):
+    import torch
+    Xd = torch.from_numpy(wl.p.X).to("cuda")
+    y = torch.from_numpy(wl.p.y).to("cuda")
+    if dtype == "f32":
+        return cg.dense_matrix(Xd), y, Xd
+    stored, scale = cg.casgd_quantize(Xd, DT_NAME[dtype])
+    del Xd
+    torch.cuda.synchronize()
+    return cg.dense_matrix(stored, scale, n=wl.n), y, stored
+
+
+def timed_fit(cg, X, y, n, b, s, eta, lam, K, W, opts_kw):
+    """Warm up W outer iterations, then time K in one launch with HIP events
+    on the stream the kernels run on. Returns (ms, x, ws)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    x = torch.zeros(n, device="cuda")
+    o = cg.opts(**opts_kw)
+    ws = cg.workspace(cg.casgd_workspace_size(X, b, s))
+    if W > 0:
+        cg.casgd_fit(X, y, x, eta, lam, b, s, SEED, 0, W, opts=o, ws=ws, stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    cg.casgd_fit(X, y, x, eta, lam, b, s, SEED, W, K, opts=o, ws=ws, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    cg.casgd_check(ws)
+    return e0.elapsed_time(e1), x, ws
+
+
+def gram_roofline(cg, X, n, b, s, dtype, reps=20):
+    """Average duration of the standalone Gram kernel (one launch per outer
+    iteration), timed with HIP events over `reps` launches."""
+    import torch
+    if s < 2:
+        return None
+    stream = torch.cuda.current_stream()
+    sb = s * b
+    G = torch.zeros(sb, sb, device="cuda")
+    ws = cg.workspace(cg.casgd_workspace_size(X, b, s))
+    for h in range(3):
+        cg.casgd_gram_margin(X, None, b, s, SEED, h, G=G, ws=ws, stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for h in range(reps):
+        cg.casgd_gram_margin(X, None, b, s, SEED, h, G=G, ws=ws, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    fl = gram_flops(b, s, n)
+    peak = PEAK[f"{dtype}_TFLOPs"]
+    ach = fl / (ms * 1e-3) / 1e12
+    return {"kernel": "k_gram (one launch: zero-counters + Gram tiles)", "bound": "mfma",
+            "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(ach / peak, 4), "us_per_launch": round(ms * 1e3, 3),
+            "flops_per_launch": fl,
+            "paper_convention_TFLOPs": round(2.0 * sb * sb * n / (ms * 1e-3) / 1e12, 3),
+            "paper_ai": round(paper_ai(b, s, n, DT_BYTES[dtype]), 1)}
+
+
+def cpu_baseline(wl: Workload, b, s, eta, lam, budget_s=15.0):
+    """The FP64 oracle (as it stands) on the host cores: outer iterations of the
+    same workload until about `budget_s` seconds have been spent."""
+    from oracle import reference as R
+    x = np.zeros(wl.n)
+    t = time.perf_counter()
+    x = R.casgd(wl.p.X, wl.p.y, x, eta, lam, b, s, SEED, 0, 1)
+    t1 = time.perf_counter() - t
+    k = max(1, min(10_000, int(budget_s / max(t1, 1e-6))))
+    t = time.perf_counter()
+    R.casgd(wl.p.X, wl.p.y, x, eta, lam, b, s, SEED, 1, k)
+    dt = time.perf_counter() - t
+    return {"value": round(s * k / dt, 2), "unit": "SGD updates/s", "cores": R.threads(),
+            "kind": "oracle",
+            "sample": f"{k} outer iterations (b={b}, s={s}) of the 2^20x2048 workload, "
+                      f"FP64 C oracle, {dt:.1f}s"}
+
+
+def eta_sweep(cg, wl: Workload, etas):
+    """One epoch of plain FP32 SGD (s = 1) per step size; test loss of each."""
+    import torch
+    X, y, _ = upload(cg, wl, "f32")
+    Xt = cg.dense_matrix(torch.from_numpy(wl.p.X_test).cuda())
+    yt = torch.from_numpy(wl.p.y_test).cuda()
+    steps = wl.m // B_C2
+    out = {}
+    for eta in etas:
+        x = torch.zeros(wl.n, device="cuda")
+        ws = cg.casgd_fit(X, y, x, eta, LAMBDA_C2, B_C2, 1, SEED, 0, steps)
+        try:
+            cg.casgd_check(ws)
+            out[eta] = float(cg.casgd_logloss(Xt, yt, x))
+        except cg.CasgdError:
+            out[eta] = float("inf")
+        log(f"[eta-sweep] eta={eta:g} test loss {out[eta]:.6f}")
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed outer iterations")
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--s", type=int, default=16)
+    ap.add_argument("--dtype", default="f32", choices=list(DT_NAME))
+    ap.add_argument("--exec-mode", type=int, default=1)
+    ap.add_argument("--variant", type=int, default=0)
+    ap.add_argument("--m", type=int, default=1 << 20)
+    ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--sweep", action="store_true")
+    ap.add_argument("--eta-sweep", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-gram", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2606_18463_amd as cg
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    cg._lib.load()
+
+    s, b, n, dtype = args.s, B_C2, args.n, args.dtype
+    wl = Workload(args.m, n, with_test=args.eta_sweep)
+    if args.eta_sweep:
+        res = eta_sweep(cg, wl, [2.0 ** k for k in range(-2, 7)])
+        print(json.dumps({"eta_sweep": res}))
+        return
+
+    X, y, _keep = upload(cg, wl, dtype)
+    # default K: about 2^16 SGD updates (a few hundred ms), W: 5% of it
+    K = args.steps if args.steps is not None else max(8, (1 << 16) // s)
+    W = args.warmup if args.warmup is not None else max(2, K // 20)
+    okw = dict(exec_mode=args.exec_mode, fused_variant=args.variant)
+    ms, x, ws = timed_fit(cg, X, y, n, b, s, ETA_C2, LAMBDA_C2, K, W, okw)
+    ups = s * K / (ms * 1e-3)
+    log(f"[bench] s={s} {dtype}: {K} outer in {ms:.2f} ms -> {ups:,.0f} updates/s")
+
+    fl = outer_flops(b, s, n) * K
+    by = outer_bytes(b, s, n, DT_BYTES[dtype]) * K
+    peak_f = PEAK[f"{dtype}_TFLOPs"]
+    ach_f = fl / (ms * 1e-3) / 1e12
+    ach_b = by / (ms * 1e-3) / 1e9
+    if s > 1:
+        roof = {"kernel": "k_fit (fused launch, all steps)", "bound": "mfma",
+                "achieved": round(ach_f, 3), "peak": peak_f, "unit": "TFLOP/s",
+                "frac": round(ach_f / peak_f, 4), "traffic": None}
+    else:
+        roof = {"kernel": "k_fit (fused launch, all steps)", "bound": "hbm",
+                "achieved": round(ach_b, 2), "peak": PEAK["hbm_GBps"], "unit": "GB/s",
+                "frac": round(ach_b / PEAK["hbm_GBps"], 5), "traffic": None}
+
+    out = {
+        "metric": "SGD updates/s (s-step CA-SGD, dense FP32 workload)",
+        "value": round(ups, 1), "unit": "SGD updates/s", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": round(ms / K, 6), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+        "config": {"workload": f"dense logistic regression X {args.m}x{n} FP32 "
+                               f"(N(0,1/n), 10% columns x10, 5% label flips), b={b}, s={s}, "
+                               f"lambda={LAMBDA_C2}, eta={ETA_C2}",
+                   "b": b, "s": s, "storage": dtype, "exec_mode": args.exec_mode,
+                   "variant": args.variant},
+        "roofline": roof,
+    }
+    if not args.no_gram and s > 1:
+        out["roofline_gram"] = gram_roofline(cg, X, n, b, s, dtype)
+    if args.sweep:
+        rows = []
+        for ss in (1, 4, 16, 32):
+            Ks = max(8, (1 << 16) // ss)
+            mss, _, _ = timed_fit(cg, X, y, n, b, ss, ETA_C2, LAMBDA_C2, Ks, max(2, Ks // 20),
+                                  dict(exec_mode=args.exec_mode))
+            rows.append({"s": ss, "updates_per_s": round(ss * Ks / (mss * 1e-3), 1),
+                         "us_per_outer": round(mss * 1e3 / Ks, 3)})
+            log(f"[sweep] s={ss}: {rows[-1]}")
+        out["sweep"] = rows
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl, b, s, ETA_C2, LAMBDA_C2)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -173,7 +173,8 @@ casgd_status casgd_sample_indices(uint64_t seed, uint64_t t0, int64_t count, int
  * Margins and Gram of outer iteration `outer_iter` (Algorithm 1, margin and
  * Gram steps): r (device, FP32, s*b) = Y x and G (device, FP32, s*b x s*b,
  * row-major) with the strict block-lower entries G[t][u] = Y_t . Y_u,
- * block(u) < block(t), written; other entries are left untouched.
+ * block(u) < block(t), written; other entries are left untouched. x and r
+ * may both be NULL to compute the Gram alone.
  */
 casgd_status casgd_gram_margin(const casgd_matrix *X, const float *x, int32_t b,
                                int32_t s, uint64_t seed, uint64_t outer_iter, float *G,
@@ -192,10 +193,10 @@ casgd_status casgd_recurrence(const float *G, const float *r, const float *yI, i
 
 /* x <- beta^s x + (eta/b) Y^T c for outer iteration `outer_iter` (Algorithm 1,
  * gradient and update steps, fused). c: device FP32 s*b (row scales are
- * applied by the library). */
+ * applied by the library). ws as for casgd_step. */
 casgd_status casgd_update(const casgd_matrix *X, float *x, const float *c, int32_t b,
                           int32_t s, uint64_t seed, uint64_t outer_iter, double eta,
-                          double lambda, void *stream);
+                          double lambda, void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------- storage formats */
 

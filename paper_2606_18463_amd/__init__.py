@@ -182,7 +182,8 @@ def casgd_gram_margin(X: MatrixRef, x, b: int, s: int, seed: int, outer_iter: in
     torch = _torch()
     sb = s * b
     G = G if G is not None else torch.zeros(sb, sb, dtype=torch.float32, device="cuda")
-    r = r if r is not None else torch.zeros(sb, dtype=torch.float32, device="cuda")
+    if x is not None and r is None:
+        r = torch.zeros(sb, dtype=torch.float32, device="cuda")
     ws, nb = _ws(ws, casgd_workspace_size(X, b, s))
     _check(_L().casgd_gram_margin(X.ref(), _ptr(x), b, s, seed, outer_iter, _ptr(G), _ptr(r),
                                   _ptr(ws), nb, _stream(stream)))
@@ -199,9 +200,10 @@ def casgd_recurrence(G, r, yI, b: int, s: int, eta: float, lam: float, prec: int
 
 
 def casgd_update(X: MatrixRef, x, c, b: int, s: int, seed: int, outer_iter: int, eta: float,
-                 lam: float, stream=None):
+                 lam: float, ws=None, stream=None):
+    ws, nb = _ws(ws, casgd_workspace_size(X, b, s))
     _check(_L().casgd_update(X.ref(), _ptr(x), _ptr(c), b, s, seed, outer_iter, eta, lam,
-                             _stream(stream)))
+                             _ptr(ws), nb, _stream(stream)))
     return x
 
 

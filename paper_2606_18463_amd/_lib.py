@@ -54,7 +54,8 @@ SIGNATURES = {
                                   c_vp]),
     "casgd_recurrence": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_dbl, c_dbl, c_i32, c_vp, c_vp,
                                  c_vp]),
-    "casgd_update": (c_i32, [PM, c_vp, c_vp, c_i32, c_i32, c_u64, c_u64, c_dbl, c_dbl, c_vp]),
+    "casgd_update": (c_i32, [PM, c_vp, c_vp, c_i32, c_i32, c_u64, c_u64, c_dbl, c_dbl, c_vp,
+                             c_sz, c_vp]),
     "casgd_quantize": (c_i32, [c_vp, c_i64, c_i64, c_i64, c_i32, c_vp, c_i64, c_vp, c_vp]),
     "casgd_logloss_workspace_size": (c_sz, [c_i64]),
     "casgd_logloss": (c_i32, [PM, c_vp, c_vp, c_i64, c_i64, c_vp, c_vp, c_sz, c_vp]),

@@ -69,15 +69,17 @@ bool dense_layout(int64_t n, int dtype, int b, int s, DenseLayout* L) {
         }
     L->needed = needed;
     const int kstep = 4 * dtype_vec(dtype);
+    const int64_t kpad = (n + kstep - 1) / kstep * kstep;
+    L->ldy = (n + 127) / 128 * 128;
     int ksplit = 1;
     if (s > 1 && needed > 0) {
         const int target = 2048;  // waves: about two per SIMD of the chip
         const int kmax = (int)std::max<int64_t>(1, n / 256);
         ksplit = std::max(1, std::min(target / needed, kmax));
     }
-    int64_t kchunk = (n + ksplit - 1) / ksplit;
+    int64_t kchunk = (kpad + ksplit - 1) / ksplit;
     kchunk = (kchunk + kstep - 1) / kstep * kstep;
-    ksplit = (int)((n + kchunk - 1) / kchunk);
+    ksplit = (int)((kpad + kchunk - 1) / kchunk);
     L->ksplit = std::max(1, ksplit);
     L->kchunk = kchunk;
     const int kw = slice_width_of(dtype);
@@ -103,10 +105,15 @@ bool dense_layout(int64_t n, int dtype, int b, int s, DenseLayout* L) {
     off = align256(off + (size_t)sb * 4);
     L->off_r = off;
     off = align256(off + (size_t)sb * 4);
-    L->off_y = off;
-    off = align256(off + (size_t)sb * 4);
-    L->off_d = off;
-    off = align256(off + (size_t)sb * 4);
+    const size_t sbpad = (size_t)L->ts * kTile;   // rows padded to whole Gram tiles
+    for (int k = 0; k < 3; ++k) {
+        L->off_Y[k] = off;
+        off = align256(off + sbpad * L->ldy * dtype_bytes(dtype));
+        L->off_yI[k] = off;
+        off = align256(off + (size_t)sb * 4);
+        L->off_sI[k] = off;
+        off = align256(off + (size_t)sb * 4);
+    }
     L->total = off;
     return true;
 }
@@ -127,6 +134,12 @@ void dense_bind(const DenseLayout& L, void* ws, Dense* P) {
     P->rp[0] = reinterpret_cast<float*>(w + L.off_rp0);
     P->rp[1] = reinterpret_cast<float*>(w + L.off_rp1);
     P->c = reinterpret_cast<float*>(w + L.off_c);
+    P->ldy = L.ldy;
+    for (int k = 0; k < 3; ++k) {
+        P->Y[k] = w + L.off_Y[k];
+        P->yI[k] = reinterpret_cast<float*>(w + L.off_yI[k]);
+        P->sI[k] = reinterpret_cast<float*>(w + L.off_sI[k]);
+    }
 }
 
 // ----------------------------------------------------------- validation
@@ -379,8 +392,8 @@ casgd_status casgd_sample_indices(uint64_t seed, uint64_t t0, int64_t count, int
 casgd_status casgd_gram_margin(const casgd_matrix* X, const float* x, int32_t b, int32_t s,
                                uint64_t seed, uint64_t outer_iter, float* G, float* r, void* ws,
                                size_t ws_bytes, void* stream) {
-    if (!x || !G || !r) {
-        set_error("x, G and r must not be NULL");
+    if (!G || (!x) != (!r)) {
+        set_error("G must not be NULL, and x and r must both be given or both be NULL");
         return CASGD_EINVAL;
     }
     Dense P;
@@ -390,7 +403,9 @@ casgd_status casgd_gram_margin(const casgd_matrix* X, const float* x, int32_t b,
     if (rc != CASGD_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
     if ((rc = run_zero(P.tile_cnt, P.ntiles, st)) != CASGD_OK) return rc;
+    if ((rc = run_gather(P, X->dtype, outer_iter, st)) != CASGD_OK) return rc;
     if ((rc = run_gram(P, X->dtype, G, outer_iter, st)) != CASGD_OK) return rc;
+    if (!x) return CASGD_OK;
     if ((rc = run_margin(P, X->dtype, outer_iter, P.rp[0], st)) != CASGD_OK) return rc;
     return run_margin_reduce(P, P.rp[0], outer_iter, r, st);
 }
@@ -424,8 +439,8 @@ casgd_status casgd_recurrence(const float* G, const float* r, const float* yI, i
 }
 
 casgd_status casgd_update(const casgd_matrix* X, float* x, const float* c, int32_t b, int32_t s,
-                          uint64_t seed, uint64_t outer_iter, double eta, double lambda,
-                          void* stream) {
+                          uint64_t seed, uint64_t outer_iter, double eta, double lambda, void* ws,
+                          size_t ws_bytes, void* stream) {
     if (!x || !c) {
         set_error("x and c must not be NULL");
         return CASGD_EINVAL;
@@ -433,9 +448,11 @@ casgd_status casgd_update(const casgd_matrix* X, float* x, const float* c, int32
     Dense P;
     DenseLayout L;
     casgd_status rc =
-        make_dense(X, nullptr, x, eta, lambda, b, s, seed, nullptr, nullptr, 0, &P, &L, false);
+        make_dense(X, nullptr, x, eta, lambda, b, s, seed, nullptr, ws, ws_bytes, &P, &L, true);
     if (rc != CASGD_OK) return rc;
-    return run_update(P, X->dtype, c, outer_iter, (hipStream_t)stream);
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = run_gather(P, X->dtype, outer_iter, st)) != CASGD_OK) return rc;
+    return run_update(P, X->dtype, c, outer_iter, st);
 }
 
 casgd_status casgd_quantize(const float* src, int64_t m, int64_t n, int64_t ld_src, int32_t dtype,

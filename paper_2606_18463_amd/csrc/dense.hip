@@ -25,8 +25,13 @@ __global__ void k_zero_u32(unsigned* p, int64_t words) {
 }
 
 template <int DT>
+__global__ __launch_bounds__(kNT) void k_gather(Dense P, uint64_t h) {
+    gather_rows<DT>(P, h, blockIdx.x * kNW + (threadIdx.x >> 6), gridDim.x * kNW);
+}
+
+template <int DT>
 __global__ __launch_bounds__(kNT) void k_gram(Dense P, float* Gout, uint64_t h, int nitems) {
-    const int item = blockIdx.x * kNW + (threadIdx.x >> 6);
+    const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * kNW + (threadIdx.x >> 6));
     if (item >= nitems) return;
     gram_item<DT>(P, Gout, h, item);
 }
@@ -48,8 +53,7 @@ __global__ __launch_bounds__(kNT) void k_margin_reduce(Dense P, const float* rp,
     if (t >= P.sb) return;
     float r = 0.f;
     for (int sl = 0; sl < P.nslices; ++sl) r += rp[(int64_t)sl * P.sb + t];
-    if (P.scale) r *= P.scale[sample_row(P.seed, h * (uint64_t)P.sb + t, P.m)];
-    r_out[t] = r;
+    r_out[t] = r * pick3(P.sI, slot_of(h))[t];
 }
 
 template <typename ACC>
@@ -89,20 +93,20 @@ __global__ __launch_bounds__(kNT) void k_fit(Dense P, uint64_t h0, int64_t H,
 
     const int nb = gridDim.x;
     const int wg = blockIdx.x;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nitems = P.ntiles * P.ksplit;
     const bool has_gram = P.s > 1;
 
     if (threadIdx.x == 0 && wg == 0 && P.t_hist) P.t_hist[0] = (int64_t)wall_clock64();
+    const int gw = wg * kNW + wave, ngw = nb * kNW;
 
-    // Prologue: Gram of h0 and the margins of h0 from the incoming x.
-    if (has_gram) {
-        const int first = (VARIANT == 2) ? 1 : 0;
-        const int nw = (nb - first) * kNW;
-        if (wg >= first)
-            for (int it = (wg - first) * kNW + wave; it < nitems; it += nw)
-                gram_item<DT>(P, P.G[0], h0, it);
-    }
+    // Prologue: gather the rows of h0 and h0+1; then the Gram of h0 and the
+    // margins of h0 from the incoming x.
+    gather_rows<DT>(P, h0, gw, ngw);
+    if (H > 1) gather_rows<DT>(P, h0 + 1, gw, ngw);
+    if (!grid_barrier(P.flags, nb, spin)) return;
+    if (has_gram)
+        for (int it = gw; it < nitems; it += ngw) gram_item<DT>(P, P.G[0], h0, it);
     for (int sl = wg; sl < P.nslices; sl += nb)
         update_margin_slice<DT, kNW>(P, sl, nullptr, 0, false, h0, true, P.rp[0], red, xs, -1);
     if (!grid_barrier(P.flags, nb, spin)) return;
@@ -111,31 +115,34 @@ __global__ __launch_bounds__(kNT) void k_fit(Dense P, uint64_t h0, int64_t H,
         const uint64_t h = h0 + (uint64_t)hh;
         const int cur = (int)(hh & 1), nxt = cur ^ 1;
         const bool more = hh + 1 < H;
+        const bool more2 = hh + 2 < H;
         const bool snap = P.snap_every > 0 && ((hh + 1) % P.snap_every) == 0;
         const int64_t snap_row = snap ? (hh + 1) / P.snap_every - 1 : -1;
         if (VARIANT == 1) {
             if (wg < P.nslices) {
-                recurrence<ACC, kNT>(P, P.G[cur], P.rp[cur], h, nullptr, nullptr, cl, nullptr, dl,
+                recurrence<ACC, kNT>(P, pick2(P.G, cur), pick2(P.rp, cur), h, nullptr, nullptr, cl, nullptr, dl,
                                      pw, tpr);
                 for (int sl = wg; sl < P.nslices; sl += nb)
-                    update_margin_slice<DT, kNW>(P, sl, cl, h, true, h + 1, more, P.rp[nxt], red,
+                    update_margin_slice<DT, kNW>(P, sl, cl, h, true, h + 1, more, pick2(P.rp, nxt), red,
                                                  xs, snap_row);
             }
             if (has_gram && more)
-                for (int it = wg * kNW + wave; it < nitems; it += nb * kNW)
-                    gram_item<DT>(P, P.G[nxt], h + 1, it);
+                for (int it = gw; it < nitems; it += ngw) gram_item<DT>(P, pick2(P.G, nxt), h + 1, it);
+            if (more2) gather_rows<DT>(P, h + 2, gw, ngw);
             if (!grid_barrier(P.flags, nb, spin)) return;
         } else {
             if (wg == 0) {
-                recurrence<ACC, kNT>(P, P.G[cur], P.rp[cur], h, nullptr, nullptr, P.c, nullptr, dl,
+                recurrence<ACC, kNT>(P, pick2(P.G, cur), pick2(P.rp, cur), h, nullptr, nullptr, P.c, nullptr, dl,
                                      pw, tpr);
-            } else if (has_gram && more) {
-                for (int it = (wg - 1) * kNW + wave; it < nitems; it += (nb - 1) * kNW)
-                    gram_item<DT>(P, P.G[nxt], h + 1, it);
+            } else {
+                const int gw1 = gw - kNW, ngw1 = ngw - kNW;
+                if (has_gram && more)
+                    for (int it = gw1; it < nitems; it += ngw1) gram_item<DT>(P, pick2(P.G, nxt), h + 1, it);
+                if (more2) gather_rows<DT>(P, h + 2, gw1, ngw1);
             }
             if (!grid_barrier(P.flags, nb, spin)) return;
             for (int sl = wg; sl < P.nslices; sl += nb)
-                update_margin_slice<DT, kNW>(P, sl, P.c, h, true, h + 1, more, P.rp[nxt], red, xs,
+                update_margin_slice<DT, kNW>(P, sl, P.c, h, true, h + 1, more, pick2(P.rp, nxt), red, xs,
                                              snap_row);
             if (!grid_barrier(P.flags, nb, spin)) return;
         }
@@ -147,6 +154,14 @@ __global__ __launch_bounds__(kNT) void k_fit(Dense P, uint64_t h0, int64_t H,
 // ------------------------------------------------------------------ host
 
 namespace {
+
+template <int DT>
+casgd_status launch_gather_t(const Dense& P, uint64_t h, hipStream_t st) {
+    const int grid = std::max(1, std::min((P.sb + kNW - 1) / kNW, 4 * device_cus()));
+    hipLaunchKernelGGL(k_gather<DT>, dim3(grid), dim3(kNT), 0, st, P, h);
+    CASGD_HIP(hipGetLastError());
+    return CASGD_OK;
+}
 
 template <int DT>
 casgd_status launch_gram_t(const Dense& P, float* Gout, uint64_t h, hipStream_t st) {
@@ -238,6 +253,15 @@ casgd_status run_zero(unsigned* p, int64_t words, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_u32, dim3(grid), dim3(256), 0, st, p, words);
     CASGD_HIP(hipGetLastError());
     return CASGD_OK;
+}
+
+casgd_status run_gather(const Dense& P, int dtype, uint64_t h, hipStream_t st) {
+    switch (dtype) {
+        case DT_F32: return launch_gather_t<DT_F32>(P, h, st);
+        case DT_BF16: return launch_gather_t<DT_BF16>(P, h, st);
+        case DT_F16: return launch_gather_t<DT_F16>(P, h, st);
+        default: return launch_gather_t<DT_FP8>(P, h, st);
+    }
 }
 
 casgd_status run_gram(const Dense& P, int dtype, float* Gout, uint64_t h, hipStream_t st) {
@@ -363,8 +387,9 @@ casgd_status run_fit(const Dense& P, int dtype, uint64_t h0, int64_t H, const Fi
             default: return dispatch_fit_dt<DT_FP8>(P, h0, H, plan, st);
         }
     }
-    // Stream-ordered: margin(h0); then per outer: gram(h), recurrence(h),
-    // update(h) fused with margin(h+1).
+    // Stream-ordered: gather(h0), margin(h0); then per outer: gram(h),
+    // gather(h+1), recurrence(h), update(h) fused with margin(h+1).
+    if ((rc = run_gather(P, dtype, h0, st)) != CASGD_OK) return rc;
     if ((rc = run_update_margin(P, dtype, nullptr, 0, 0, h0, 1, P.rp[0], -1, st)) != CASGD_OK)
         return rc;
     for (int64_t hh = 0; hh < H; ++hh) {
@@ -373,6 +398,7 @@ casgd_status run_fit(const Dense& P, int dtype, uint64_t h0, int64_t H, const Fi
         const bool snap = P.snap_every > 0 && ((hh + 1) % P.snap_every) == 0;
         const int64_t snap_row = snap ? (hh + 1) / P.snap_every - 1 : -1;
         if ((rc = run_gram(P, dtype, P.G[0], h, st)) != CASGD_OK) return rc;
+        if (more && (rc = run_gather(P, dtype, h + 1, st)) != CASGD_OK) return rc;
         if ((rc = run_recurrence(P, P.G[0], P.rp[0], h, nullptr, nullptr, P.c, nullptr,
                                  plan.recur64 != 0, st)) != CASGD_OK)
             return rc;

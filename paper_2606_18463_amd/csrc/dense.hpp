@@ -10,9 +10,10 @@ namespace casgd {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTile = 64;   // Gram tile edge in sampled rows
-constexpr int kLPR = 8;     // lanes per row in the update / margin passes
+constexpr int kLPR = 4;     // lanes per row in the update / margin passes
 
 // One dense problem: inputs, scalars, launch geometry and workspace views.
 struct Dense {
@@ -30,16 +31,33 @@ struct Dense {
     int ksplit;             // K splits per tile
     int64_t kchunk;         // K elements per split (multiple of the K step)
     int nslices;            // column slices of the update / margin passes
+    int64_t ldy;            // row stride (elements) of the gathered rows: n rounded up to 128
     unsigned* flags;        // FLAG_* words
     unsigned* tile_cnt;     // split-K arrival counters, one per tile
     float* G[2];            // sb x sb, row-major, strict block-lower part used
     float* Gpart;           // ntiles * ksplit * 4096 split-K partial tiles
     float* rp[2];           // nslices x sb partial margins
     float* c;               // sb corrected residual weights
+    void* Y[3];             // gathered rows of outer iteration h in slot h % 3 (sb x ldy)
+    float* yI[3];           // their labels
+    float* sI[3];           // their row scales (1 when X has none)
     float* x_hist;          // snapshots or nullptr
     int64_t* t_hist;        // snapshot clocks or nullptr
     int64_t snap_every;
 };
+
+__device__ __forceinline__ int slot_of(uint64_t h) { return (int)(h % 3ull); }
+
+// Buffer selection by explicit selects: indexing the by-value kernel argument
+// with a run-time index would force the whole struct into scratch memory.
+template <typename T>
+__device__ __forceinline__ T pick3(const T (&a)[3], int k) {
+    return k == 0 ? a[0] : (k == 1 ? a[1] : a[2]);
+}
+template <typename T>
+__device__ __forceinline__ T pick2(const T (&a)[2], int k) {
+    return k == 0 ? a[0] : a[1];
+}
 
 // Sum over groups of G consecutive lanes, G a power of two chosen at run time.
 template <typename T>
@@ -77,13 +95,17 @@ __device__ __forceinline__ bool tile_needed(const Dense& P, int TJ, int TI) {
     return (TI * kTile) / P.b < rlast / P.b;
 }
 
+// MFMA instructions per 16-byte operand vector: FP32 4 (16x16x4), BF16/FP16 1
+// (16x16x32), FP8 2 (16x16x32 on 8 bytes each).
 template <int DT>
-__device__ __forceinline__ void mfma_step(const V16& a, const V16& b, v4f& acc) {
+constexpr int mfma_per_vec() { return DT == DT_F32 ? 4 : (DT == DT_FP8 ? 2 : 1); }
+
+// The q-th MFMA of a 16-byte operand pair: acc += A_q B_q^T on a 16x16 tile.
+template <int DT>
+__device__ __forceinline__ void mfma_q(const V16& a, const V16& b, int q, v4f& acc) {
     if constexpr (DT == DT_F32) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w[q]),
-                                                       __uint_as_float(b.w[q]), acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w[q]), __uint_as_float(b.w[q]),
+                                                   acc, 0, 0, 0);
     } else if constexpr (DT == DT_BF16) {
         bf16x8 av, bv;
         __builtin_memcpy(&av, &a, 16);
@@ -95,12 +117,9 @@ __device__ __forceinline__ void mfma_step(const V16& a, const V16& b, v4f& acc) 
         __builtin_memcpy(&bv, &b, 16);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bv, acc, 0, 0, 0);
     } else {
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const long av = (long)(((uint64_t)a.w[2 * q + 1] << 32) | a.w[2 * q]);
-            const long bv = (long)(((uint64_t)b.w[2 * q + 1] << 32) | b.w[2 * q]);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv, acc, 0, 0, 0);
-        }
+        const long av = (long)(((uint64_t)a.w[2 * q + 1] << 32) | a.w[2 * q]);
+        const long bv = (long)(((uint64_t)b.w[2 * q + 1] << 32) | b.w[2 * q]);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv, acc, 0, 0, 0);
     }
 }
 
@@ -130,14 +149,64 @@ __device__ __forceinline__ void store_tile(const Dense& P, float* Gout, int TJ, 
     }
 }
 
+// Gather the s*b sampled rows of outer iteration h (Algorithm 1, sampling
+// and gather steps) into slot h % 3: row t of Y is X[idx_t, :], zero-padded
+// to ldy elements, with its label and row scale; rows sb .. up to the next
+// multiple of kTile are zero. One wave copies one row; every lane keeps up
+// to eight 16-byte loads in flight.
+template <int DT>
+__device__ __forceinline__ void gather_rows(const Dense& P, uint64_t h, int wave_id, int nwaves) {
+    using T = typename Store<DT>::T;
+    constexpr int VEC = Store<DT>::kVec;
+    constexpr int U = 8;
+    const int slot = slot_of(h);
+    T* Y = static_cast<T*>(pick3(P.Y, slot));
+    const T* X = static_cast<const T*>(P.X);
+    const int lane = threadIdx.x & 63;
+    const int64_t nv = P.ldy / VEC;
+    const uint64_t t0 = h * (uint64_t)P.sb;
+    const V16 zero = {{0u, 0u, 0u, 0u}};
+    const int sbpad = (P.sb + kTile - 1) / kTile * kTile;
+    for (int t = wave_id; t < sbpad; t += nwaves) {
+        T* dst = Y + (int64_t)t * P.ldy;
+        if (t >= P.sb) {  // padding rows of the last Gram tile: zeros
+            for (int64_t v = lane; v < nv; v += 64)
+                *reinterpret_cast<uint4*>(dst + v * VEC) = make_uint4(0u, 0u, 0u, 0u);
+            continue;
+        }
+        const int64_t row = sample_row(P.seed, t0 + t, P.m);
+        const T* src = X + row * P.ld;
+        for (int64_t v0 = lane; v0 < nv; v0 += 64 * U) {
+            V16 buf[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t v = v0 + 64 * u;
+                buf[u] = v < nv ? load_v16<DT>(src, v * VEC, P.n) : zero;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t v = v0 + 64 * u;
+                if (v < nv)
+                    *reinterpret_cast<uint4*>(dst + v * VEC) =
+                        make_uint4(buf[u].w[0], buf[u].w[1], buf[u].w[2], buf[u].w[3]);
+            }
+        }
+        if (lane == 0) {
+            pick3(P.yI, slot)[t] = P.y ? P.y[row] : 0.0f;
+            pick3(P.sI, slot)[t] = P.scale ? P.scale[row] : 1.0f;
+        }
+    }
+}
+
 // One work item = one K split of one 64x64 tile, computed by one wave with
-// operands loaded straight from the sampled rows of X into registers (both
-// MFMA operands are K-contiguous rows of Y, so no LDS transpose is needed).
+// operands loaded from the gathered rows straight into registers (both MFMA
+// operands are K-contiguous rows of Y, so no LDS transpose is needed).
 // Lane l owns row l%16 of each 16-row sub-tile and the 16-byte K segment
 // (l/16); within a K step every (lane group, vector element) pair maps to a
-// distinct k, identically for both operands, so the products pair up.
+// distinct k, identically for both operands, so the products pair up. Rows
+// are zero-padded to ldy and to a multiple of kTile, so no load is guarded.
 template <int DT>
-__device__ void gram_item(const Dense& P, float* Gout, uint64_t h, int item) {
+__device__ __forceinline__ void gram_item(const Dense& P, float* Gout, uint64_t h, int item) {
     using T = typename Store<DT>::T;
     constexpr int VEC = Store<DT>::kVec;
     constexpr int KSTEP = 4 * VEC;
@@ -149,66 +218,76 @@ __device__ void gram_item(const Dense& P, float* Gout, uint64_t h, int item) {
     if (!tile_needed(P, TJ, TI)) return;
     const bool diag = TJ == TI;
     const int li = lane & 15, lg = lane >> 4;
-    const T* X = static_cast<const T*>(P.X);
-    const uint64_t t0 = h * (uint64_t)P.sb;
+    const int slot = slot_of(h);
+    const T* Y = static_cast<const T*>(pick3(P.Y, slot));
 
+    // Rows beyond sb are zero padding in the gathered buffer, so every load is
+    // unconditional.
     const T* ra[4];
     const T* rb[4];
-    bool va[4], vb[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-        const int t = TJ * kTile + 16 * a + li;
-        va[a] = t < P.sb;
-        ra[a] = X + (va[a] ? sample_row(P.seed, t0 + t, P.m) : 0) * P.ld;
-        const int u = TI * kTile + 16 * a + li;
-        vb[a] = u < P.sb;
-        rb[a] = X + (vb[a] ? sample_row(P.seed, t0 + u, P.m) : 0) * P.ld;
+        ra[a] = Y + (int64_t)(TJ * kTile + 16 * a + li) * P.ldy + VEC * lg;
+        rb[a] = Y + (int64_t)(TI * kTile + 16 * a + li) * P.ldy + VEC * lg;
     }
 
+    const int64_t kpad = (P.n + KSTEP - 1) / KSTEP * KSTEP;
     const int64_t k0 = (int64_t)split * P.kchunk;
-    const int64_t k1 = min(P.n, k0 + P.kchunk);
+    const int64_t k1 = min(kpad, k0 + P.kchunk);
     v4f acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[a][c] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    const V16 zero = {{0u, 0u, 0u, 0u}};
-    V16 A[4], B[4], An[4], Bn[4];
-    auto load = [&](V16 (&Av)[4], V16 (&Bv)[4], int64_t k) {
-        const int64_t kk = k + VEC * lg;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) Av[a] = va[a] ? load_v16<DT>(ra[a], kk, P.n) : zero;
-        if (!diag) {
-#pragma unroll
-            for (int c = 0; c < 4; ++c) Bv[c] = vb[c] ? load_v16<DT>(rb[c], kk, P.n) : zero;
-        }
+    auto ld16 = [&](const T* p, int64_t k) -> V16 {
+        const u32x4 q = *reinterpret_cast<const u32x4*>(p + k);
+        V16 r;
+        r.w[0] = q[0]; r.w[1] = q[1]; r.w[2] = q[2]; r.w[3] = q[3];
+        return r;
     };
-    if (k0 < k1) load(A, B, k0);
-    for (int64_t k = k0; k < k1; k += KSTEP) {
-        const bool more = k + KSTEP < k1;
-        if (more) load(An, Bn, k + KSTEP);
+    // Ping-pong operand buffers: the loads of step k+1 are in flight while the
+    // MFMAs of step k run (no register copies, so no early wait). Diagonal
+    // tiles load B too (same addresses as A, served by the L1).
+    V16 A0[4], B0[4], A1[4], B1[4];
+    auto load = [&](V16 (&Av)[4], V16 (&Bv)[4], int64_t k) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < 4; ++a) Av[a] = ld16(ra[a], k);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) mfma_step<DT>(A[a], diag ? A[c] : B[c], acc[a][c]);
-        if (more) {
+        for (int c = 0; c < 4; ++c) Bv[c] = ld16(rb[c], k);
+    };
+    auto mma = [&](const V16 (&Av)[4], const V16 (&Bv)[4]) {
+        // q outermost: 16 independent accumulators between dependent MFMAs
 #pragma unroll
-            for (int a = 0; a < 4; ++a) { A[a] = An[a]; B[a] = Bn[a]; }
-        }
+        for (int q = 0; q < mfma_per_vec<DT>(); ++q)
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) mfma_q<DT>(Av[a], Bv[c], q, acc[a][c]);
+    };
+    if (k0 < k1) load(A0, B0, k0);
+#pragma unroll 1
+    for (int64_t k = k0; k < k1; k += 2 * KSTEP) {
+        if (k + KSTEP < k1) load(A1, B1, k + KSTEP);
+        mma(A0, B0);
+        if (k + KSTEP >= k1) break;
+        if (k + 2 * KSTEP < k1) load(A0, B0, k + 2 * KSTEP);
+        mma(A1, B1);
     }
+    (void)diag;
 
     // Row scales of the tile's rows (output layout) and columns.
     float sr[4][4], sc[4];
+    const float* sI = pick3(P.sI, slot);
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int t = TJ * kTile + 16 * a + 4 * lg + v;
-            sr[a][v] = (P.scale && t < P.sb) ? P.scale[sample_row(P.seed, t0 + t, P.m)] : 1.0f;
+            sr[a][v] = (P.scale && t < P.sb) ? sI[t] : 1.0f;
         }
         const int u = TI * kTile + 16 * a + li;
-        sc[a] = (P.scale && u < P.sb) ? P.scale[sample_row(P.seed, t0 + u, P.m)] : 1.0f;
+        sc[a] = (P.scale && u < P.sb) ? sI[u] : 1.0f;
     }
 
     if (P.ksplit == 1) {
@@ -252,42 +331,58 @@ __device__ void gram_item(const Dense& P, float* Gout, uint64_t h, int item) {
 //   x <- beta^s x + alpha * sum_t c_t * scale_t * Y_t[slice]      (outer h)
 // and then optionally the partial margins of outer hn on the (new) slice:
 //   rp_out[slice][t] = Y_t[slice] . x[slice]   (row scale applied later).
-// A row is read by kLPR lanes with 16-byte loads; NW waves share the rows.
+// A row segment is read by kLPR lanes with 16-byte loads from the gathered
+// rows; NW waves share the rows and every lane keeps U rows in flight.
 // Uses LDS `red` (NW * width floats) and `xs` (width floats).
 template <int DT, int NW>
-__device__ void update_margin_slice(const Dense& P, int slice, const float* c, uint64_t h,
+__device__ __forceinline__ void update_margin_slice(const Dense& P, int slice, const float* c, uint64_t h,
                                     bool do_update, uint64_t hn, bool do_margin, float* rp_out,
                                     float* red, float* xs, int64_t snap_row) {
     using T = typename Store<DT>::T;
     constexpr int VEC = Store<DT>::kVec;
     constexpr int KW = slice_width<DT>();
     constexpr int RPW = kWave / kLPR;
+    constexpr int U = 8;
+    constexpr int STRIDE = NW * RPW;
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
     const int sub = lane % kLPR, rg = lane / kLPR;
     const int64_t col0 = (int64_t)slice * KW;
     const int64_t kl = col0 + sub * VEC;
-    const T* X = static_cast<const T*>(P.X);
+    const V16 zero = {{0u, 0u, 0u, 0u}};
 
     if (do_update) {
-        const uint64_t t0 = h * (uint64_t)P.sb;
+        const int slot = slot_of(h);
+        const T* Y = static_cast<const T*>(pick3(P.Y, slot)) + kl;
+        const float* sI = pick3(P.sI, slot);
         float acc[VEC];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
-        for (int t = w * RPW + rg; t < P.sb; t += NW * RPW) {
-            const int64_t row = sample_row(P.seed, t0 + t, P.m);
-            float ct = c[t];
-            if (P.scale) ct *= P.scale[row];
-            const V16 v = load_v16<DT>(X + row * P.ld, kl, P.n);
+        for (int t0 = w * RPW + rg; t0 < P.sb; t0 += STRIDE * U) {
+            V16 v[U];
+            float ct[U];
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) acc[e] = fmaf(v16_elem<DT>(v, e), ct, acc[e]);
+            for (int u = 0; u < U; ++u) {
+                const int t = t0 + u * STRIDE;
+                const bool ok = t < P.sb;
+                if (ok) {
+                    const uint4 q = *reinterpret_cast<const uint4*>(Y + (int64_t)t * P.ldy);
+                    v[u].w[0] = q.x; v[u].w[1] = q.y; v[u].w[2] = q.z; v[u].w[3] = q.w;
+                    ct[u] = c[t] * sI[t];
+                } else {
+                    v[u] = zero;
+                    ct[u] = 0.f;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) acc[e] = fmaf(v16_elem<DT>(v[u], e), ct[u], acc[e]);
         }
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) {
-            acc[e] += shfl_xor(acc[e], 8);
-            acc[e] += shfl_xor(acc[e], 16);
-            acc[e] += shfl_xor(acc[e], 32);
-        }
+        for (int e = 0; e < VEC; ++e)
+#pragma unroll
+            for (int off = kLPR; off < kWave; off <<= 1) acc[e] += shfl_xor(acc[e], off);
         if (rg == 0) {
 #pragma unroll
             for (int e = 0; e < VEC; ++e) red[w * KW + sub * VEC + e] = acc[e];
@@ -316,18 +411,31 @@ __device__ void update_margin_slice(const Dense& P, int slice, const float* c, u
         __syncthreads();
     }
     if (do_margin) {
-        const uint64_t t0 = hn * (uint64_t)P.sb;
+        const T* Y = static_cast<const T*>(pick3(P.Y, slot_of(hn))) + kl;
         float xv[VEC];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) xv[e] = xs[sub * VEC + e];
-        for (int t = w * RPW + rg; t < P.sb; t += NW * RPW) {
-            const int64_t row = sample_row(P.seed, t0 + t, P.m);
-            const V16 v = load_v16<DT>(X + row * P.ld, kl, P.n);
-            float d = 0.f;
+        for (int t0 = w * RPW + rg; t0 < P.sb; t0 += STRIDE * U) {
+            V16 v[U];
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) d = fmaf(v16_elem<DT>(v, e), xv[e], d);
-            d = group_sum<kLPR>(d);
-            if (sub == 0) rp_out[(int64_t)slice * P.sb + t] = d;
+            for (int u = 0; u < U; ++u) {
+                const int t = t0 + u * STRIDE;
+                if (t < P.sb) {
+                    const uint4 q = *reinterpret_cast<const uint4*>(Y + (int64_t)t * P.ldy);
+                    v[u].w[0] = q.x; v[u].w[1] = q.y; v[u].w[2] = q.z; v[u].w[3] = q.w;
+                } else {
+                    v[u] = zero;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = t0 + u * STRIDE;
+                float d = 0.f;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) d = fmaf(v16_elem<DT>(v[u], e), xv[e], d);
+                d = group_sum<kLPR>(d);
+                if (sub == 0 && t < P.sb) rp_out[(int64_t)slice * P.sb + t] = d;
+            }
         }
     }
     __syncthreads();
@@ -340,13 +448,17 @@ __device__ void update_margin_slice(const Dense& P, int slice, const float* c, u
 //   z_t = beta^j r_t + alpha * sum_{i<j} beta^(j-1-i) (G_{t, block i} . delta_i)
 //   delta_t = y_t / (1 + exp(y_t z_t));  c_t = beta^(s-1-j) delta_t
 // r_t and y_t come either from the partial margins rp (summed over slices,
-// times the row scale) and the sampled labels, or directly from r_in / y_in.
+// times the row scale) and the gathered labels, or directly from r_in / y_in.
 // Writes c (global or LDS) and optionally delta_out. Uses LDS `dl` (sb ACC)
-// and `pw` (s+1 ACC).
+// and `pw` (s+1 ACC). The row prefix G[t, 0:jb) does not depend on earlier
+// residuals, so each thread issues its loads in batches of kRB independent
+// 16-byte loads before consuming them.
+constexpr int kRB = 16;
+
 template <typename ACC, int NT>
-__device__ void recurrence(const Dense& P, const float* G, const float* rp, uint64_t h,
-                           const float* r_in, const float* y_in, float* c, float* delta_out,
-                           ACC* dl, ACC* pw, int TPR) {
+__device__ __forceinline__ void recurrence(const Dense& P, const float* G, const float* rp,
+                                           uint64_t h, const float* r_in, const float* y_in,
+                                           float* c, float* delta_out, ACC* dl, ACC* pw, int TPR) {
     const int tid = threadIdx.x;
     const int b = P.b, s = P.s, sb = P.sb;
     if (tid == 0) {
@@ -359,35 +471,49 @@ __device__ void recurrence(const Dense& P, const float* G, const float* rp, uint
     const int RPP = NT / TPR;         // rows per pass
     const int sub = tid % TPR;
     const bool vec4 = (b % 4) == 0;
-    const uint64_t t0 = h * (uint64_t)sb;
+    const int slot = slot_of(h);
     for (int j = 0; j < s; ++j) {
         for (int q0 = 0; q0 < b; q0 += RPP) {
             const int q = q0 + tid / TPR;
             const bool active = q < b;
             const int t = j * b + q;
             ACC rr = 0, acc = 0;
-            int64_t row = 0;
             if (active) {
                 if (!r_in) {
-                    row = sample_row(P.seed, t0 + t, P.m);
                     for (int sl = sub; sl < P.nslices; sl += TPR) rr += (ACC)rp[(int64_t)sl * sb + t];
                     rr = group_sum_rt(rr, TPR);
                 }
                 const float* grow = G + (int64_t)t * sb;
-                for (int i = 0; i < j; ++i) {
-                    const float* g = grow + i * b;
-                    const ACC* d = dl + i * b;
-                    ACC part = 0;
-                    if (vec4) {
-                        for (int p = 4 * sub; p < b; p += 4 * TPR) {
-                            const float4 gv = *reinterpret_cast<const float4*>(g + p);
-                            part += (ACC)gv.x * d[p] + (ACC)gv.y * d[p + 1] +
-                                    (ACC)gv.z * d[p + 2] + (ACC)gv.w * d[p + 3];
+                if (vec4) {
+                    const int nv = (j * b) >> 2;    // float4 chunks of the prefix
+                    const float4* g4 = reinterpret_cast<const float4*>(grow);
+                    for (int base = sub; base < nv; base += kRB * TPR) {
+                        float4 g[kRB];
+#pragma unroll
+                        for (int k = 0; k < kRB; ++k) {
+                            const int v = base + k * TPR;
+                            g[k] = v < nv ? g4[v] : make_float4(0.f, 0.f, 0.f, 0.f);
                         }
-                    } else {
-                        for (int p = sub; p < b; p += TPR) part += (ACC)g[p] * d[p];
+#pragma unroll
+                        for (int k = 0; k < kRB; ++k) {
+                            const int v = base + k * TPR;
+                            if (v < nv) {
+                                const int u = 4 * v;
+                                const ACC* d = dl + u;
+                                const ACC part = (ACC)g[k].x * d[0] + (ACC)g[k].y * d[1] +
+                                                 (ACC)g[k].z * d[2] + (ACC)g[k].w * d[3];
+                                acc += pw[j - 1 - u / b] * part;
+                            }
+                        }
                     }
-                    acc += pw[j - 1 - i] * part;
+                } else {
+                    for (int i = 0; i < j; ++i) {
+                        const float* g = grow + i * b;
+                        const ACC* d = dl + i * b;
+                        ACC part = 0;
+                        for (int p = sub; p < b; p += TPR) part += (ACC)g[p] * d[p];
+                        acc += pw[j - 1 - i] * part;
+                    }
                 }
                 acc = group_sum_rt(acc, TPR);
             }
@@ -397,8 +523,8 @@ __device__ void recurrence(const Dense& P, const float* G, const float* rp, uint
                     r = (ACC)r_in[t];
                     yv = (ACC)y_in[t];
                 } else {
-                    r = rr * (ACC)(P.scale ? P.scale[row] : 1.0f);
-                    yv = (ACC)P.y[row];
+                    r = rr * (ACC)pick3(P.sI, slot)[t];
+                    yv = (ACC)pick3(P.yI, slot)[t];
                 }
                 const ACC z = pw[j] * r + alpha * acc;
                 const ACC d = yv / ((ACC)1 + exp(yv * z));

@@ -23,15 +23,15 @@ int dtype_bytes(int dtype);
 int dtype_vec(int dtype);          // elements per 16-byte vector
 int slice_width_of(int dtype);     // columns per update / margin slice
 
-constexpr int kNT = 512;           // threads per workgroup of the dense kernels
+constexpr int kNT = 256;           // threads per workgroup of the dense kernels
 constexpr int kNW = kNT / 64;
 
 // Workspace layout of one dense problem (byte offsets, 256-byte aligned).
 struct DenseLayout {
     int sb, ts, ntiles, needed, ksplit, nslices;
-    int64_t kchunk;
+    int64_t kchunk, ldy;
     size_t off_flags, off_tilecnt, off_G0, off_G1, off_Gpart, off_rp0, off_rp1, off_c, off_r,
-        off_y, off_d, total;
+        off_Y[3], off_yI[3], off_sI[3], total;
 };
 
 bool dense_layout(int64_t n, int dtype, int b, int s, DenseLayout* L);
@@ -49,6 +49,7 @@ struct FitPlan {
 casgd_status plan_fit(const Dense& P, int dtype, const casgd_opts* o, int64_t H, FitPlan* plan);
 casgd_status run_fit(const Dense& P, int dtype, uint64_t h0, int64_t H, const FitPlan& plan,
                      hipStream_t st);
+casgd_status run_gather(const Dense& P, int dtype, uint64_t h, hipStream_t st);
 casgd_status run_gram(const Dense& P, int dtype, float* Gout, uint64_t h, hipStream_t st);
 casgd_status run_margin(const Dense& P, int dtype, uint64_t h, float* rp_out, hipStream_t st);
 casgd_status run_margin_reduce(const Dense& P, const float* rp, uint64_t h, float* r_out,
