@@ -160,8 +160,46 @@ casgd_status casgd_fit(const casgd_matrix *X, const float *y, float *x, double e
                        void *ws, size_t ws_bytes, void *stream);
 
 /* Reports the device flags of a workspace after synchronising `stream`:
- * CASGD_OK, CASGD_ENONFINITE or CASGD_ETIMEOUT. */
+ * CASGD_OK, CASGD_ENONFINITE, CASGD_ETIMEOUT, or CASGD_EUNSUPPORTED when a
+ * sparse tail bucket overflowed. */
 casgd_status casgd_check(const void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------- CSR X and lambda lanes */
+
+/*
+ * A CSR X is split once per (X, b, s) into dense "head" columns (the most
+ * frequent ones, at most 512, expected to occur at least once per outer block)
+ * and sparse "tail" columns. The head panel's Gram runs on MFMA; tail
+ * intersections are accumulated per G row in a fixed order. Tail columns may
+ * occur at most 64 times in one outer block of sampled rows; more raises a
+ * device flag reported by casgd_check as CASGD_EUNSUPPORTED.
+ */
+
+/* Workspace bytes for a CSR X with these b, s and up to `lanes` lanes (a
+ * dense X is not supported here). Reads row_ptr (synchronous). b must be a
+ * multiple of 4. */
+casgd_status casgd_path_workspace_size(const casgd_matrix *X, int32_t b, int32_t s,
+                                       int32_t lanes, size_t *bytes);
+
+/* Prepare a workspace for a CSR X: column frequencies, head/tail split,
+ * cleared buckets. Synchronous. Required once per (X, b, s, workspace) before
+ * casgd_fit / casgd_step / casgd_fit_path on that CSR X; `lanes` is the largest
+ * lane count that will be used. Its cost is not part of any iteration. */
+casgd_status casgd_sparse_prepare(const casgd_matrix *X, int32_t b, int32_t s, int32_t lanes,
+                                  void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Regularisation path: L lanes (1 <= L <= 64) with strengths lambdas (host,
+ * L doubles, >= 0) share the sampled rows, the gathered block and the Gram
+ * matrix of every outer iteration; each lane runs its own residual
+ * corrections and update (beta_l = 1 - eta*lambda_l). x_lanes (device, FP32,
+ * n x L, lane fastest) is updated in place; lane l equals a casgd_fit with
+ * lambda_l on the same seed. CSR X only. One fused launch.
+ */
+casgd_status casgd_fit_path(const casgd_matrix *X, const float *y, float *x_lanes,
+                            const double *lambdas, int32_t L, double eta, int32_t b, int32_t s,
+                            uint64_t seed, uint64_t outer_begin, int64_t n_outer,
+                            const casgd_opts *opts, void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------- pieces of the iteration */
 

@@ -18,6 +18,7 @@ __all__ = [
     "casgd_workspace_size", "casgd_reset", "casgd_step", "casgd_fit", "casgd_check",
     "casgd_sample_indices", "casgd_gram_margin", "casgd_recurrence", "casgd_update",
     "casgd_quantize", "casgd_logloss", "casgd_colstats", "casgd_version",
+    "casgd_path_workspace_size", "casgd_sparse_prepare", "casgd_fit_path",
 ]
 
 
@@ -167,6 +168,31 @@ def casgd_step(X: MatrixRef, y, x, eta: float, lam: float, b: int, s: int, seed:
     ws, nb = _ws(ws, casgd_workspace_size(X, b, s))
     _check(_L().casgd_step(X.ref(), _ptr(y), _ptr(x), eta, lam, b, s, seed, outer_iter,
                            _opts_ref(opts), _ptr(ws), nb, _stream(stream)))
+    return ws
+
+
+def casgd_path_workspace_size(X: MatrixRef, b: int, s: int, lanes: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(_L().casgd_path_workspace_size(X.ref(), b, s, lanes, ctypes.byref(out)))
+    return int(out.value)
+
+
+def casgd_sparse_prepare(X: MatrixRef, b: int, s: int, lanes: int = 1, ws=None, stream=None):
+    """Prepare (and if needed allocate) a workspace for a CSR X; returns it."""
+    ws, nb = _ws(ws, casgd_path_workspace_size(X, b, s, lanes))
+    _check(_L().casgd_sparse_prepare(X.ref(), b, s, lanes, _ptr(ws), nb, _stream(stream)))
+    return ws
+
+
+def casgd_fit_path(X: MatrixRef, y, x_lanes, lambdas, eta: float, b: int, s: int, seed: int,
+                   outer_begin: int = 0, n_outer: int = 1, opts=None, ws=None, stream=None):
+    """Regularisation path on a CSR X: x_lanes (n x L) in place, one lane per lambda."""
+    lam = (ctypes.c_double * len(lambdas))(*[float(v) for v in lambdas])
+    if ws is None:
+        ws = casgd_sparse_prepare(X, b, s, len(lambdas), stream=stream)
+    _check(_L().casgd_fit_path(X.ref(), _ptr(y), _ptr(x_lanes), lam, len(lambdas), eta, b, s,
+                               seed, outer_begin, n_outer, _opts_ref(opts), _ptr(ws), ws.numel(),
+                               _stream(stream)))
     return ws
 
 

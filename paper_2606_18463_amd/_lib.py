@@ -49,6 +49,10 @@ SIGNATURES = {
     "casgd_fit": (c_i32, [PM, c_vp, c_vp, c_dbl, c_dbl, c_i32, c_i32, c_u64, c_u64, c_i64, PO,
                           c_vp, c_sz, c_vp]),
     "casgd_check": (c_i32, [c_vp, c_sz, c_vp]),
+    "casgd_path_workspace_size": (c_i32, [PM, c_i32, c_i32, c_i32, ctypes.POINTER(c_sz)]),
+    "casgd_sparse_prepare": (c_i32, [PM, c_i32, c_i32, c_i32, c_vp, c_sz, c_vp]),
+    "casgd_fit_path": (c_i32, [PM, c_vp, c_vp, ctypes.POINTER(c_dbl), c_i32, c_dbl, c_i32, c_i32,
+                               c_u64, c_u64, c_i64, PO, c_vp, c_sz, c_vp]),
     "casgd_sample_indices": (c_i32, [c_u64, c_u64, c_i64, c_i64, c_vp, c_vp]),
     "casgd_gram_margin": (c_i32, [PM, c_vp, c_i32, c_i32, c_u64, c_u64, c_vp, c_vp, c_vp, c_sz,
                                   c_vp]),

@@ -346,7 +346,42 @@ casgd_status casgd_check(const void* ws, size_t ws_bytes, void* stream) {
         set_error("a margin, residual or weight became NaN or Inf");
         return CASGD_ENONFINITE;
     }
+    unsigned ov = 0;
+    CASGD_HIP(hipMemcpy(&ov, static_cast<const unsigned*>(ws) + 2, sizeof ov,
+                        hipMemcpyDeviceToHost));
+    if (ov) {
+        set_error("a sparse tail-column bucket overflowed (results invalid)");
+        return CASGD_EUNSUPPORTED;
+    }
     return CASGD_OK;
+}
+
+casgd_status casgd_path_workspace_size(const casgd_matrix* X, int32_t b, int32_t s,
+                                       int32_t lanes, size_t* bytes) {
+    if (!bytes) {
+        set_error("bytes is NULL");
+        return CASGD_EINVAL;
+    }
+    if (X && X->layout == CASGD_CSR) return sparse_workspace_size(X, b, s, lanes, bytes);
+    set_error("lambda lanes need a CSR X");
+    return CASGD_EUNSUPPORTED;
+}
+
+casgd_status casgd_sparse_prepare(const casgd_matrix* X, int32_t b, int32_t s, int32_t lanes,
+                                  void* ws, size_t ws_bytes, void* stream) {
+    return sparse_prepare(X, b, s, lanes, ws, ws_bytes, stream);
+}
+
+casgd_status casgd_fit_path(const casgd_matrix* X, const float* y, float* x_lanes,
+                            const double* lambdas, int32_t L, double eta, int32_t b, int32_t s,
+                            uint64_t seed, uint64_t outer_begin, int64_t n_outer,
+                            const casgd_opts* opts, void* ws, size_t ws_bytes, void* stream) {
+    if (!X || X->layout != CASGD_CSR) {
+        set_error("lambda lanes need a CSR X");
+        return CASGD_EUNSUPPORTED;
+    }
+    return sparse_fit(X, y, x_lanes, lambdas, L, eta, b, s, seed, outer_begin, n_outer, opts, ws,
+                      ws_bytes, stream);
 }
 
 casgd_status casgd_fit(const casgd_matrix* X, const float* y, float* x, double eta,

@@ -20,6 +20,8 @@ casgd_status run_colstats(const casgd_matrix* X, float* stats, double* partial, 
 
 casgd_status sparse_workspace_size(const casgd_matrix* X, int32_t b, int32_t s, int32_t lanes,
                                    size_t* bytes);
+casgd_status sparse_prepare(const casgd_matrix* X, int32_t b, int32_t s, int32_t lanes, void* ws,
+                            size_t ws_bytes, void* stream);
 casgd_status sparse_fit(const casgd_matrix* X, const float* y, float* x_lanes,
                         const double* lambdas_host, int32_t L, double eta, int32_t b, int32_t s,
                         uint64_t seed, uint64_t outer_begin, int64_t n_outer,
