@@ -201,6 +201,45 @@ casgd_status casgd_fit_path(const casgd_matrix *X, const float *y, float *x_lane
                             uint64_t seed, uint64_t outer_begin, int64_t n_outer,
                             const casgd_opts *opts, void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------ many problems */
+
+/* One problem of a batched launch. X dense (all problems of a batch share
+ * one storage dtype); the other fields as for casgd_fit; ws/ws_bytes is this
+ * problem's own workspace (casgd_workspace_size). groups = workgroups given to
+ * this problem (0: chosen by the library from a cost model); variant and
+ * recur_prec as casgd_opts.fused_variant / recur_prec (0 = automatic). */
+typedef struct {
+    casgd_matrix X;
+    const float *y;
+    float *x;
+    double eta, lambda;
+    int32_t b, s;
+    uint64_t seed;
+    uint64_t outer_begin;
+    int64_t n_outer;
+    void *ws;
+    size_t ws_bytes;
+    int32_t groups;
+    int32_t variant;
+    int32_t recur_prec;
+    int32_t reserved;
+} casgd_problem;
+
+/* Bytes of the device table workspace of a batch of `count` problems. */
+size_t casgd_batch_table_size(int32_t count);
+
+/*
+ * Fit `count` independent dense problems (probs: host array) in one
+ * cooperative launch: each problem runs its whole fit (all of its outer
+ * iterations, as casgd_fit would) on its own group of workgroups with its own
+ * grid barrier, so short and long problems proceed concurrently. The problem
+ * table is uploaded to `table` (device, casgd_batch_table_size bytes) with a
+ * synchronous copy before the launch. spin_limit as in casgd_opts (0 =
+ * default). Results equal casgd_fit per problem for the same variant.
+ */
+casgd_status casgd_fit_batch(const casgd_problem *probs, int32_t count, int64_t spin_limit,
+                             void *table, size_t table_bytes, void *stream);
+
 /* ------------------------------------------------- pieces of the iteration */
 
 /* Sample rows (Algorithm 1, first step): out[q] = row of sample t0+q. */
@@ -251,6 +290,67 @@ casgd_status casgd_update(const casgd_matrix *X, float *x, const float *c, int32
 casgd_status casgd_quantize(const float *src, int64_t m, int64_t n, int64_t ld_src,
                             int32_t dtype, void *dst, int64_t ld_dst, float *row_scale,
                             void *stream);
+
+/* Same as casgd_quantize of the column-scaled matrix X diag(col_scale)
+ * (col_scale: device, FP32, n), each product rounded to FP32 first. Used to
+ * apply a diagonal preconditioner d as X diag(sqrt(d)). */
+casgd_status casgd_quantize_scaled(const float *src, int64_t m, int64_t n, int64_t ld_src,
+                                   const float *col_scale, int32_t dtype, void *dst,
+                                   int64_t ld_dst, float *row_scale, void *stream);
+
+/* ------------------------------------------------ learned preconditioner */
+
+/*
+ * A 4 -> 64 -> 2 MLP maps per-column statistics of X to a per-feature step
+ * scale and a step size (not part of the paper). Parameters (device, FP32,
+ * 450 floats): W1[64][4], b1[64], W2[2][64], b2[2]; for input row f:
+ * pre = W1 f + b1, h = relu(pre), out = W2 h + b2. out[0] predicts log d_k,
+ * out[1] is averaged over a problem's columns into its log step size. Every
+ * reduction runs in a fixed order.
+ */
+#define CASGD_MLP_PARAMS 450
+
+/* feats (device, N x 4) = (log(1 + |stats|) - norm[0:4]) / norm[4:8];
+ * stats (device, N x 4) as written by casgd_colstats; norm (device, 8). */
+casgd_status casgd_mlp_features(const float *stats, int64_t N, const float *norm, float *feats,
+                                void *stream);
+
+/* out (device, N x 2); pre (device, N x 64, the hidden pre-activations kept
+ * for the backward pass) may be NULL. */
+casgd_status casgd_mlp_forward(const float *params, const float *feats, int64_t N, float *out,
+                               float *pre, void *stream);
+
+/* Workspace of casgd_mlp_loss_grad / casgd_mlp_backward for N rows, P problems. */
+size_t casgd_mlp_workspace_size(int64_t N, int32_t P);
+
+/*
+ * Training loss over P problems whose rows are seg_off[p] .. seg_off[p+1]-1
+ * (seg_off: device, int64, P+1):
+ *   L = mean_rows (out0 - t_d)^2 + w_eta * mean_p (mean_{rows of p} out1 - t_eta[p])^2
+ * loss (device, FP64, 1) and g_out = dL/dout (device, N x 2).
+ */
+casgd_status casgd_mlp_loss_grad(const float *out, const int64_t *seg_off, int32_t P, int64_t N,
+                                 const float *t_d, const float *t_eta, float w_eta, double *loss,
+                                 float *g_out, void *ws, size_t ws_bytes, void *stream);
+
+/* grad (device, 450) = dL/dparams given g_out, from feats and pre of the forward. */
+casgd_status casgd_mlp_backward(const float *params, const float *feats, const float *pre,
+                                const float *g_out, int64_t N, int32_t P, float *grad, void *ws,
+                                size_t ws_bytes, void *stream);
+
+/* One Adam step (Kingma and Ba, 2015) with bias correction, t >= 1:
+ * m1 = b1 m1 + (1-b1) g; m2 = b2 m2 + (1-b2) g^2;
+ * params -= lr (m1/(1-b1^t)) / (sqrt(m2/(1-b2^t)) + eps). All device arrays. */
+casgd_status casgd_adam_step(float *params, const float *grad, float *m1, float *m2,
+                             int32_t count, int64_t t, float lr, float beta1, float beta2,
+                             float eps, void *stream);
+
+/* Diagonal of the Hessian of the mean logistic loss plus lambda at x:
+ * hdiag_k = m^-1 sum_i s(z_i)(1 - s(z_i)) X_ik^2 + lambda, z_i = X_i . x
+ * (device, FP32, n). Dense X. ws (device) of casgd_hess_diag_workspace_size. */
+size_t casgd_hess_diag_workspace_size(const casgd_matrix *X);
+casgd_status casgd_hess_diag(const casgd_matrix *X, const float *x, double lambda, float *hdiag,
+                             void *ws, size_t ws_bytes, void *stream);
 
 /* --------------------------------------------------- measurement support */
 

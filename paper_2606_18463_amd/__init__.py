@@ -19,7 +19,12 @@ __all__ = [
     "casgd_sample_indices", "casgd_gram_margin", "casgd_recurrence", "casgd_update",
     "casgd_quantize", "casgd_logloss", "casgd_colstats", "casgd_version",
     "casgd_path_workspace_size", "casgd_sparse_prepare", "casgd_fit_path",
+    "casgd_fit_batch", "casgd_quantize_scaled", "casgd_mlp_features", "casgd_mlp_forward",
+    "casgd_mlp_loss_grad", "casgd_mlp_backward", "casgd_adam_step", "casgd_hess_diag",
+    "MLP_PARAMS",
 ]
+
+MLP_PARAMS = 450
 
 
 class CasgdError(RuntimeError):
@@ -196,6 +201,30 @@ def casgd_fit_path(X: MatrixRef, y, x_lanes, lambdas, eta: float, b: int, s: int
     return ws
 
 
+def casgd_fit_batch(problems, spin_limit: int = 0, stream=None):
+    """Fit many dense problems in one launch. `problems`: list of dicts with keys
+    X (MatrixRef), y, x, eta, lam, b, s, seed and optionally outer_begin,
+    n_outer, ws, groups, variant, recur_prec. Returns the list of workspaces."""
+    n = len(problems)
+    arr = (_lib.Problem * n)()
+    keep = []
+    for i, q in enumerate(problems):
+        X = q["X"]
+        ws = q.get("ws")
+        if ws is None:
+            ws = workspace(casgd_workspace_size(X, q["b"], q["s"]))
+        keep.append((X, ws))
+        arr[i] = _lib.Problem(X=X.struct, y=_ptr(q["y"]), x=_ptr(q["x"]), eta=q["eta"],
+                              lam=q["lam"], b=q["b"], s=q["s"], seed=q["seed"],
+                              outer_begin=q.get("outer_begin", 0), n_outer=q.get("n_outer", 1),
+                              ws=_ptr(ws), ws_bytes=ws.numel(), groups=q.get("groups", 0),
+                              variant=q.get("variant", 0), recur_prec=q.get("recur_prec", 0),
+                              reserved=0)
+    tb = workspace(int(_L().casgd_batch_table_size(n)))
+    _check(_L().casgd_fit_batch(arr, n, spin_limit, _ptr(tb), tb.numel(), _stream(stream)))
+    return [w for _, w in keep]
+
+
 def casgd_sample_indices(seed: int, t0: int, count: int, m: int, out=None, stream=None):
     torch = _torch()
     out = out if out is not None else torch.empty(count, dtype=torch.int64, device="cuda")
@@ -247,6 +276,80 @@ def casgd_quantize(src, dtype: int, ld_dst: int | None = None, stream=None):
     _check(_L().casgd_quantize(_ptr(src), m, n, src.stride(0), dtype, _ptr(dst), ld, _ptr(scale),
                                _stream(stream)))
     return dst, scale
+
+
+def casgd_quantize_scaled(src, col_scale, dtype: int, ld_dst: int | None = None, stream=None):
+    """casgd_quantize of src * col_scale (columns scaled, e.g. by sqrt(d))."""
+    torch = _torch()
+    m, n = src.shape
+    vec = {F32: 4, BF16: 8, F16: 8, FP8E4M3: 16}[dtype]
+    ld = ld_dst or ((n + vec - 1) // vec * vec)
+    tdt = {F32: torch.float32, BF16: torch.bfloat16, F16: torch.float16,
+           FP8E4M3: torch.uint8}[dtype]
+    dst = torch.empty(m, ld, dtype=tdt, device=src.device)
+    scale = torch.empty(m, dtype=torch.float32, device=src.device) if dtype == FP8E4M3 else None
+    _check(_L().casgd_quantize_scaled(_ptr(src), m, n, src.stride(0), _ptr(col_scale), dtype,
+                                      _ptr(dst), ld, _ptr(scale), _stream(stream)))
+    return dst, scale
+
+
+def casgd_mlp_features(stats, norm, stream=None):
+    torch = _torch()
+    feats = torch.empty_like(stats)
+    _check(_L().casgd_mlp_features(_ptr(stats), stats.shape[0], _ptr(norm), _ptr(feats),
+                                   _stream(stream)))
+    return feats
+
+
+def casgd_mlp_forward(params, feats, want_pre: bool = True, stream=None):
+    torch = _torch()
+    N = feats.shape[0]
+    out = torch.empty(N, 2, dtype=torch.float32, device=feats.device)
+    pre = torch.empty(N, 64, dtype=torch.float32, device=feats.device) if want_pre else None
+    _check(_L().casgd_mlp_forward(_ptr(params), _ptr(feats), N, _ptr(out), _ptr(pre),
+                                  _stream(stream)))
+    return out, pre
+
+
+def _mlp_ws(N, P):
+    return workspace(int(_L().casgd_mlp_workspace_size(N, P)))
+
+
+def casgd_mlp_loss_grad(out, seg_off, t_d, t_eta, w_eta: float = 1.0, ws=None, stream=None):
+    torch = _torch()
+    N, P = out.shape[0], seg_off.numel() - 1
+    loss = torch.empty(1, dtype=torch.float64, device=out.device)
+    g = torch.empty_like(out)
+    ws = ws if ws is not None else _mlp_ws(N, P)
+    _check(_L().casgd_mlp_loss_grad(_ptr(out), _ptr(seg_off), P, N, _ptr(t_d), _ptr(t_eta),
+                                    w_eta, _ptr(loss), _ptr(g), _ptr(ws), ws.numel(),
+                                    _stream(stream)))
+    return loss, g
+
+
+def casgd_mlp_backward(params, feats, pre, g_out, P: int = 1, ws=None, stream=None):
+    torch = _torch()
+    N = feats.shape[0]
+    grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=feats.device)
+    ws = ws if ws is not None else _mlp_ws(N, P)
+    _check(_L().casgd_mlp_backward(_ptr(params), _ptr(feats), _ptr(pre), _ptr(g_out), N, P,
+                                   _ptr(grad), _ptr(ws), ws.numel(), _stream(stream)))
+    return grad
+
+
+def casgd_adam_step(params, grad, m1, m2, t: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8,
+                    stream=None):
+    _check(_L().casgd_adam_step(_ptr(params), _ptr(grad), _ptr(m1), _ptr(m2), params.numel(), t,
+                                lr, beta1, beta2, eps, _stream(stream)))
+
+
+def casgd_hess_diag(X: MatrixRef, x, lam: float, stream=None):
+    torch = _torch()
+    out = torch.empty(X.n, dtype=torch.float32, device="cuda")
+    ws = workspace(int(_L().casgd_hess_diag_workspace_size(X.ref())))
+    _check(_L().casgd_hess_diag(X.ref(), _ptr(x), lam, _ptr(out), _ptr(ws), ws.numel(),
+                                _stream(stream)))
+    return out
 
 
 def casgd_logloss(X: MatrixRef, y, xs, stream=None):

@@ -34,6 +34,13 @@ class Opts(ctypes.Structure):
                 ("fused_variant", c_i32), ("grid_blocks", c_i32)]
 
 
+class Problem(ctypes.Structure):
+    _fields_ = [("X", Matrix), ("y", c_vp), ("x", c_vp), ("eta", c_dbl), ("lam", c_dbl),
+                ("b", c_i32), ("s", c_i32), ("seed", c_u64), ("outer_begin", c_u64),
+                ("n_outer", c_i64), ("ws", c_vp), ("ws_bytes", c_sz), ("groups", c_i32),
+                ("variant", c_i32), ("recur_prec", c_i32), ("reserved", c_i32)]
+
+
 PM = ctypes.POINTER(Matrix)
 PO = ctypes.POINTER(Opts)
 
@@ -49,6 +56,8 @@ SIGNATURES = {
     "casgd_fit": (c_i32, [PM, c_vp, c_vp, c_dbl, c_dbl, c_i32, c_i32, c_u64, c_u64, c_i64, PO,
                           c_vp, c_sz, c_vp]),
     "casgd_check": (c_i32, [c_vp, c_sz, c_vp]),
+    "casgd_batch_table_size": (c_sz, [c_i32]),
+    "casgd_fit_batch": (c_i32, [ctypes.POINTER(Problem), c_i32, c_i64, c_vp, c_sz, c_vp]),
     "casgd_path_workspace_size": (c_i32, [PM, c_i32, c_i32, c_i32, ctypes.POINTER(c_sz)]),
     "casgd_sparse_prepare": (c_i32, [PM, c_i32, c_i32, c_i32, c_vp, c_sz, c_vp]),
     "casgd_fit_path": (c_i32, [PM, c_vp, c_vp, ctypes.POINTER(c_dbl), c_i32, c_dbl, c_i32, c_i32,
@@ -61,6 +70,18 @@ SIGNATURES = {
     "casgd_update": (c_i32, [PM, c_vp, c_vp, c_i32, c_i32, c_u64, c_u64, c_dbl, c_dbl, c_vp,
                              c_sz, c_vp]),
     "casgd_quantize": (c_i32, [c_vp, c_i64, c_i64, c_i64, c_i32, c_vp, c_i64, c_vp, c_vp]),
+    "casgd_quantize_scaled": (c_i32, [c_vp, c_i64, c_i64, c_i64, c_vp, c_i32, c_vp, c_i64, c_vp,
+                                      c_vp]),
+    "casgd_mlp_features": (c_i32, [c_vp, c_i64, c_vp, c_vp, c_vp]),
+    "casgd_mlp_forward": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp, c_vp]),
+    "casgd_mlp_workspace_size": (c_sz, [c_i64, c_i32]),
+    "casgd_mlp_loss_grad": (c_i32, [c_vp, c_vp, c_i32, c_i64, c_vp, c_vp, ctypes.c_float, c_vp,
+                                    c_vp, c_vp, c_sz, c_vp]),
+    "casgd_mlp_backward": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i64, c_i32, c_vp, c_vp, c_sz, c_vp]),
+    "casgd_adam_step": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i32, c_i64, ctypes.c_float,
+                                ctypes.c_float, ctypes.c_float, ctypes.c_float, c_vp]),
+    "casgd_hess_diag_workspace_size": (c_sz, [PM]),
+    "casgd_hess_diag": (c_i32, [PM, c_vp, c_dbl, c_vp, c_vp, c_sz, c_vp]),
     "casgd_logloss_workspace_size": (c_sz, [c_i64]),
     "casgd_logloss": (c_i32, [PM, c_vp, c_vp, c_i64, c_i64, c_vp, c_vp, c_sz, c_vp]),
     "casgd_colstats_workspace_size": (c_sz, [PM]),

@@ -6,6 +6,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
+#include <algorithm>
 
 #include "internal.hpp"
 #include "misc.hpp"
@@ -415,6 +417,132 @@ casgd_status casgd_step(const casgd_matrix* X, const float* y, float* x, double 
     return casgd_fit(X, y, x, eta, lambda, b, s, seed, outer_iter, 1, opts, ws, ws_bytes, stream);
 }
 
+static constexpr int kBatchMaxWG = 4096;
+
+size_t casgd_batch_table_size(int32_t count) {
+    if (count < 1) return 0;
+    return align256((size_t)count * sizeof(Dense)) + (size_t)kBatchMaxWG * sizeof(int2);
+}
+
+// Cost model of one problem's fit on g workgroups: H outer iterations of
+// (fixed part: recurrence stream of G_L on one CU + barriers) + (parallel part:
+// Gram flops + row traffic spread over g workgroups). Rates are per workgroup.
+static double batch_time(const Dense& P, int dtype, int g) {
+    const double gl = 4.0 * P.b * (double)P.b * P.s * (P.s - 1) / 2.0;
+    const double fixed = gl / 100e9 + 4e-6;
+    const double flop_rate = dtype == CASGD_F32 ? 0.3e12 : 2.0e12;
+    const double par = (double)P.s * (P.s - 1) * P.b * P.b * P.n / flop_rate +
+                       3.0 * P.sb * (double)P.ldy * dtype_bytes(dtype) / 40e9;
+    return (double)P.H * (fixed + par / g);
+}
+
+casgd_status casgd_fit_batch(const casgd_problem* probs, int32_t count, int64_t spin_limit,
+                             void* table, size_t table_bytes, void* stream) {
+    if (!probs || count < 1) {
+        set_error("need at least one problem");
+        return CASGD_EINVAL;
+    }
+    const size_t need = casgd_batch_table_size(count);
+    casgd_status rc;
+    if ((rc = check_ws(table, table_bytes, need)) != CASGD_OK) return rc;
+    const int dtype = probs[0].X.dtype;
+    std::vector<Dense> D((size_t)count);
+    std::vector<int> groups((size_t)count), minimum((size_t)count);
+    size_t lds = 0;
+    hipStream_t st = (hipStream_t)stream;
+    for (int i = 0; i < count; ++i) {
+        const casgd_problem& q = probs[i];
+        if (q.X.dtype != dtype) {
+            set_error("problem %d: all problems of a batch must share one storage dtype", i);
+            return CASGD_EINVAL;
+        }
+        if (!q.y || !q.x || q.n_outer < 0) {
+            set_error("problem %d: y and x must not be NULL and n_outer >= 0", i);
+            return CASGD_EINVAL;
+        }
+        DenseLayout L;
+        casgd_opts o;
+        std::memset(&o, 0, sizeof o);
+        o.recur_prec = q.recur_prec;
+        o.fused_variant = q.variant;
+        rc = make_dense(&q.X, q.y, q.x, q.eta, q.lambda, q.b, q.s, q.seed, &o, q.ws, q.ws_bytes,
+                        &D[i], &L, true);
+        if (rc != CASGD_OK) {
+            std::string m = casgd_last_error();
+            set_error("problem %d: %s", i, m.c_str());
+            return rc;
+        }
+        FitPlan plan;
+        if ((rc = plan_fit(D[i], dtype, &o, q.n_outer, &plan)) != CASGD_OK) return rc;
+        D[i].h0 = q.outer_begin;
+        D[i].H = q.n_outer;
+        D[i].variant = plan.variant;
+        D[i].recur64 = plan.recur64;
+        D[i].tpr = recurrence_tpr(kNT, q.b);
+        lds = std::max(lds, fit_lds(D[i], dtype, plan.recur64));
+        minimum[i] = plan.variant == 2 ? 2 : 1;
+        groups[i] = q.groups;
+        if (q.groups > 0 && q.groups < minimum[i]) {
+            set_error("problem %d: variant 2 needs at least 2 workgroups", i);
+            return CASGD_EINVAL;
+        }
+    }
+    if (lds > 65536) {
+        set_error("a problem of the batch needs more LDS than the fused kernel has");
+        return CASGD_EUNSUPPORTED;
+    }
+    const int maxg = std::min(batch_max_grid(dtype, lds), kBatchMaxWG);
+    int fixed = 0, need_min = 0;
+    for (int i = 0; i < count; ++i) {
+        if (groups[i] > 0) fixed += groups[i];
+        else need_min += minimum[i];
+    }
+    if (fixed + need_min > maxg) {
+        set_error("batch needs %d workgroups, at most %d can be resident", fixed + need_min, maxg);
+        return CASGD_EUNSUPPORTED;
+    }
+    // Automatic groups: start from the minimum and give each further
+    // workgroup to the problem whose modelled finishing time is largest.
+    for (int i = 0; i < count; ++i)
+        if (groups[i] == 0) groups[i] = -minimum[i];
+    int spare = maxg - fixed - need_min;
+    while (spare > 0) {
+        int worst = -1;
+        double wt = -1.0;
+        for (int i = 0; i < count; ++i) {
+            if (groups[i] >= 0) continue;
+            const double t = batch_time(D[i], dtype, -groups[i]);
+            if (t > wt) { wt = t; worst = i; }
+        }
+        if (worst < 0) break;
+        const double gain = wt - batch_time(D[worst], dtype, -groups[worst] + 1);
+        if (gain <= 1e-3 * wt) break;
+        --groups[worst];
+        --spare;
+    }
+    std::vector<int2> wgmap;
+    for (int i = 0; i < count; ++i) {
+        const int g = std::abs(groups[i]);
+        D[i].gsize = g;
+        for (int r = 0; r < g; ++r) wgmap.push_back(make_int2(i, r));
+    }
+    const int grid = (int)wgmap.size();
+    for (int i = 0; i < count; ++i) {
+        if ((rc = run_zero(D[i].tile_cnt, D[i].ntiles, st)) != CASGD_OK) return rc;
+        if ((rc = run_zero(D[i].flags + FLAG_BAR_COUNT, FLAG_WORDS - FLAG_BAR_COUNT, st)) != CASGD_OK)
+            return rc;
+    }
+    char* tb = static_cast<char*>(table);
+    Dense* tdev = reinterpret_cast<Dense*>(tb);
+    int2* mdev = reinterpret_cast<int2*>(tb + align256((size_t)count * sizeof(Dense)));
+    CASGD_HIP(hipMemcpyAsync(tdev, D.data(), D.size() * sizeof(Dense), hipMemcpyHostToDevice, st));
+    CASGD_HIP(hipMemcpyAsync(mdev, wgmap.data(), wgmap.size() * sizeof(int2), hipMemcpyHostToDevice,
+                             st));
+    CASGD_HIP(hipStreamSynchronize(st));
+    const unsigned long long spin = spin_limit > 0 ? (unsigned long long)spin_limit : (1ull << 24);
+    return run_fit_batch(tdev, mdev, grid, dtype, lds, spin, st);
+}
+
 casgd_status casgd_sample_indices(uint64_t seed, uint64_t t0, int64_t count, int64_t m,
                                   int64_t* out, void* stream) {
     if (count < 0 || m < 1 || (count > 0 && !out)) {
@@ -501,7 +629,99 @@ casgd_status casgd_quantize(const float* src, int64_t m, int64_t n, int64_t ld_s
         set_error("FP8-E4M3 needs row_scale");
         return CASGD_EINVAL;
     }
-    return run_quantize(src, m, n, ld_src, dtype, dst, ld_dst, row_scale, (hipStream_t)stream);
+    return run_quantize(src, m, n, ld_src, dtype, dst, ld_dst, row_scale, nullptr,
+                        (hipStream_t)stream);
+}
+
+casgd_status casgd_quantize_scaled(const float* src, int64_t m, int64_t n, int64_t ld_src,
+                                   const float* col_scale, int32_t dtype, void* dst, int64_t ld_dst,
+                                   float* row_scale, void* stream) {
+    const int eb = dtype_bytes(dtype);
+    if (!src || !dst || !col_scale || m < 1 || n < 1 || ld_src < n || ld_dst < n || !eb) {
+        set_error("bad arguments to casgd_quantize_scaled");
+        return CASGD_EINVAL;
+    }
+    if (dtype == CASGD_FP8E4M3 && !row_scale) {
+        set_error("FP8-E4M3 needs row_scale");
+        return CASGD_EINVAL;
+    }
+    return run_quantize(src, m, n, ld_src, dtype, dst, ld_dst, row_scale, col_scale,
+                        (hipStream_t)stream);
+}
+
+casgd_status casgd_mlp_features(const float* stats, int64_t N, const float* norm, float* feats,
+                                void* stream) {
+    if (N < 0 || (N > 0 && (!stats || !norm || !feats))) {
+        set_error("bad arguments to casgd_mlp_features");
+        return CASGD_EINVAL;
+    }
+    return run_mlp_features(stats, N, norm, feats, (hipStream_t)stream);
+}
+
+casgd_status casgd_mlp_forward(const float* params, const float* feats, int64_t N, float* out,
+                               float* pre, void* stream) {
+    if (N < 0 || !params || (N > 0 && (!feats || !out))) {
+        set_error("bad arguments to casgd_mlp_forward");
+        return CASGD_EINVAL;
+    }
+    return run_mlp_forward(params, feats, N, out, pre, (hipStream_t)stream);
+}
+
+size_t casgd_mlp_workspace_size(int64_t N, int32_t P) {
+    return align256(mlp_loss_ws(P > 0 ? P : 1)) + align256(mlp_backward_ws(N));
+}
+
+casgd_status casgd_mlp_loss_grad(const float* out, const int64_t* seg_off, int32_t P, int64_t N,
+                                 const float* t_d, const float* t_eta, float w_eta, double* loss,
+                                 float* g_out, void* ws, size_t ws_bytes, void* stream) {
+    casgd_status rc;
+    if (!out || !seg_off || P < 1 || N < 1 || !t_d || !t_eta || !loss || !g_out) {
+        set_error("bad arguments to casgd_mlp_loss_grad");
+        return CASGD_EINVAL;
+    }
+    if ((rc = check_ws(ws, ws_bytes, casgd_mlp_workspace_size(N, P))) != CASGD_OK) return rc;
+    return run_mlp_loss_grad(out, seg_off, P, N, t_d, t_eta, w_eta, loss, g_out,
+                             static_cast<double*>(ws), (hipStream_t)stream);
+}
+
+casgd_status casgd_mlp_backward(const float* params, const float* feats, const float* pre,
+                                const float* g_out, int64_t N, int32_t P, float* grad, void* ws,
+                                size_t ws_bytes, void* stream) {
+    casgd_status rc;
+    if (!params || !grad || N < 0 || (N > 0 && (!feats || !pre || !g_out))) {
+        set_error("bad arguments to casgd_mlp_backward");
+        return CASGD_EINVAL;
+    }
+    if ((rc = check_ws(ws, ws_bytes, casgd_mlp_workspace_size(N, P))) != CASGD_OK) return rc;
+    float* partial = reinterpret_cast<float*>(static_cast<char*>(ws) +
+                                              align256(mlp_loss_ws(P > 0 ? P : 1)));
+    return run_mlp_backward(params, feats, pre, g_out, N, grad, partial, (hipStream_t)stream);
+}
+
+casgd_status casgd_adam_step(float* params, const float* grad, float* m1, float* m2,
+                             int32_t count, int64_t t, float lr, float beta1, float beta2,
+                             float eps, void* stream) {
+    if (!params || !grad || !m1 || !m2 || count < 1 || t < 1) {
+        set_error("bad arguments to casgd_adam_step");
+        return CASGD_EINVAL;
+    }
+    return run_adam(params, grad, m1, m2, count, t, lr, beta1, beta2, eps, (hipStream_t)stream);
+}
+
+size_t casgd_hess_diag_workspace_size(const casgd_matrix* X) {
+    return X ? hess_ws(X) : 0;
+}
+
+casgd_status casgd_hess_diag(const casgd_matrix* X, const float* x, double lambda, float* hdiag,
+                             void* ws, size_t ws_bytes, void* stream) {
+    casgd_status rc;
+    if (!x || !hdiag) {
+        set_error("x and hdiag must not be NULL");
+        return CASGD_EINVAL;
+    }
+    if ((rc = check_dense(X)) != CASGD_OK) return rc;
+    if ((rc = check_ws(ws, ws_bytes, hess_ws(X))) != CASGD_OK) return rc;
+    return run_hess_diag(X, x, lambda, hdiag, ws, (hipStream_t)stream);
 }
 
 size_t casgd_logloss_workspace_size(int64_t count) {

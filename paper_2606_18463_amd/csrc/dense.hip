@@ -78,11 +78,12 @@ __host__ __device__ inline size_t fit_lds_bytes(int sb, int s, int acc_bytes, in
     return off;
 }
 
-template <int DT, typename ACC, int VARIANT>
-__global__ __launch_bounds__(kNT) void k_fit(Dense P, uint64_t h0, int64_t H,
-                                             unsigned long long spin, int tpr) {
+// One problem's whole fit on the workgroups wg = 0 .. nb-1 of its group (the
+// grid, or one group of a batched launch), with the group's own barrier.
+template <int DT, typename ACC>
+__device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigned long long spin,
+                                         unsigned char* lds) {
     constexpr int KW = slice_width<DT>();
-    extern __shared__ __align__(16) unsigned char lds[];
     ACC* dl = reinterpret_cast<ACC*>(lds);
     ACC* pw = dl + P.sb;
     size_t off = (size_t)P.sb * sizeof(ACC) + (size_t)(P.s + 1) * sizeof(ACC);
@@ -91,11 +92,12 @@ __global__ __launch_bounds__(kNT) void k_fit(Dense P, uint64_t h0, int64_t H,
     float* red = cl + P.sb;
     float* xs = red + kNW * KW;
 
-    const int nb = gridDim.x;
-    const int wg = blockIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nitems = P.ntiles * P.ksplit;
     const bool has_gram = P.s > 1;
+    const uint64_t h0 = P.h0;
+    const int64_t H = P.H;
+    const int tpr = P.tpr;
 
     if (threadIdx.x == 0 && wg == 0 && P.t_hist) P.t_hist[0] = (int64_t)wall_clock64();
     const int gw = wg * kNW + wave, ngw = nb * kNW;
@@ -118,37 +120,61 @@ __global__ __launch_bounds__(kNT) void k_fit(Dense P, uint64_t h0, int64_t H,
         const bool more2 = hh + 2 < H;
         const bool snap = P.snap_every > 0 && ((hh + 1) % P.snap_every) == 0;
         const int64_t snap_row = snap ? (hh + 1) / P.snap_every - 1 : -1;
-        if (VARIANT == 1) {
+        if (P.variant == 1) {
             if (wg < P.nslices) {
-                recurrence<ACC, kNT>(P, pick2(P.G, cur), pick2(P.rp, cur), h, nullptr, nullptr, cl, nullptr, dl,
-                                     pw, tpr);
+                recurrence<ACC, kNT>(P, pick2(P.G, cur), pick2(P.rp, cur), h, nullptr, nullptr, cl,
+                                     nullptr, dl, pw, tpr);
                 for (int sl = wg; sl < P.nslices; sl += nb)
-                    update_margin_slice<DT, kNW>(P, sl, cl, h, true, h + 1, more, pick2(P.rp, nxt), red,
-                                                 xs, snap_row);
+                    update_margin_slice<DT, kNW>(P, sl, cl, h, true, h + 1, more, pick2(P.rp, nxt),
+                                                 red, xs, snap_row);
             }
             if (has_gram && more)
-                for (int it = gw; it < nitems; it += ngw) gram_item<DT>(P, pick2(P.G, nxt), h + 1, it);
+                for (int it = gw; it < nitems; it += ngw)
+                    gram_item<DT>(P, pick2(P.G, nxt), h + 1, it);
             if (more2) gather_rows<DT>(P, h + 2, gw, ngw);
             if (!grid_barrier(P.flags, nb, spin)) return;
         } else {
             if (wg == 0) {
-                recurrence<ACC, kNT>(P, pick2(P.G, cur), pick2(P.rp, cur), h, nullptr, nullptr, P.c, nullptr, dl,
-                                     pw, tpr);
+                recurrence<ACC, kNT>(P, pick2(P.G, cur), pick2(P.rp, cur), h, nullptr, nullptr, P.c,
+                                     nullptr, dl, pw, tpr);
             } else {
                 const int gw1 = gw - kNW, ngw1 = ngw - kNW;
                 if (has_gram && more)
-                    for (int it = gw1; it < nitems; it += ngw1) gram_item<DT>(P, pick2(P.G, nxt), h + 1, it);
+                    for (int it = gw1; it < nitems; it += ngw1)
+                        gram_item<DT>(P, pick2(P.G, nxt), h + 1, it);
                 if (more2) gather_rows<DT>(P, h + 2, gw1, ngw1);
             }
             if (!grid_barrier(P.flags, nb, spin)) return;
             for (int sl = wg; sl < P.nslices; sl += nb)
-                update_margin_slice<DT, kNW>(P, sl, P.c, h, true, h + 1, more, pick2(P.rp, nxt), red, xs,
-                                             snap_row);
+                update_margin_slice<DT, kNW>(P, sl, P.c, h, true, h + 1, more, pick2(P.rp, nxt), red,
+                                             xs, snap_row);
             if (!grid_barrier(P.flags, nb, spin)) return;
         }
         if (snap && wg == 0 && threadIdx.x == 0 && P.t_hist)
             P.t_hist[snap_row + 1] = (int64_t)wall_clock64();
     }
+}
+
+template <int DT, typename ACC>
+__global__ __launch_bounds__(kNT) void k_fit(Dense P, unsigned long long spin) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    fit_body<DT, ACC>(P, blockIdx.x, gridDim.x, spin, lds);
+}
+
+// Many problems in one cooperative launch: workgroup w runs problem
+// wgmap[w].x as member wgmap[w].y of that problem's group (table[p].gsize
+// workgroups, contiguous). Each problem keeps its own workspace and barrier.
+template <int DT>
+__global__ __launch_bounds__(kNT) void k_fit_batch(const Dense* table, const int2* wgmap,
+                                                   unsigned long long spin) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int2 me = wgmap[blockIdx.x];
+    const Dense& P = table[__builtin_amdgcn_readfirstlane(me.x)];
+    const int wg = __builtin_amdgcn_readfirstlane(me.y);
+    if (P.recur64)
+        fit_body<DT, double>(P, wg, P.gsize, spin, lds);
+    else
+        fit_body<DT, float>(P, wg, P.gsize, spin, lds);
 }
 
 // ------------------------------------------------------------------ host
@@ -188,64 +214,83 @@ size_t rec_lds(const Dense& P) {
     return (size_t)P.sb * sizeof(ACC) + (size_t)(P.s + 1) * sizeof(ACC);
 }
 
-template <int DT, typename ACC, int V>
-casgd_status launch_fit_t(const Dense& P, uint64_t h0, int64_t H, const FitPlan& plan,
-                          hipStream_t st) {
+template <int DT, typename ACC>
+casgd_status launch_fit_t(const Dense& P, const FitPlan& plan, hipStream_t st) {
     const size_t lds = fit_lds_bytes(P.sb, P.s, (int)sizeof(ACC), slice_width<DT>());
-    auto kern = k_fit<DT, ACC, V>;
+    auto kern = k_fit<DT, ACC>;
     if (lds > 65536) {
         set_error("fused kernel needs %zu bytes of LDS (s*b too large for it)", lds);
         return CASGD_EUNSUPPORTED;
     }
     Dense Pc = P;
-    uint64_t h0v = h0;
-    int64_t Hv = H;
     unsigned long long spin = plan.spin;
-    int tpr = recurrence_tpr(kNT, P.b);
-    void* args[] = {&Pc, &h0v, &Hv, &spin, &tpr};
+    void* args[] = {&Pc, &spin};
     CASGD_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(plan.grid),
                                          dim3(kNT), args, (unsigned)lds, st));
     return CASGD_OK;
 }
 
-template <int DT, typename ACC, int V>
+template <int DT, typename ACC>
 int fit_max_grid(const Dense& P) {
     const size_t lds = fit_lds_bytes(P.sb, P.s, (int)sizeof(ACC), slice_width<DT>());
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void*>(k_fit<DT, ACC, V>), kNT, lds) != hipSuccess)
+            &per_cu, reinterpret_cast<const void*>(k_fit<DT, ACC>), kNT, lds) != hipSuccess)
         return 0;
     return per_cu * device_cus();
 }
 
 template <int DT>
-casgd_status dispatch_fit_dt(const Dense& P, uint64_t h0, int64_t H, const FitPlan& plan,
-                             hipStream_t st) {
-    if (plan.recur64) {
-        return plan.variant == 1 ? launch_fit_t<DT, double, 1>(P, h0, H, plan, st)
-                                 : launch_fit_t<DT, double, 2>(P, h0, H, plan, st);
-    }
-    return plan.variant == 1 ? launch_fit_t<DT, float, 1>(P, h0, H, plan, st)
-                             : launch_fit_t<DT, float, 2>(P, h0, H, plan, st);
+casgd_status dispatch_fit_dt(const Dense& P, const FitPlan& plan, hipStream_t st) {
+    return plan.recur64 ? launch_fit_t<DT, double>(P, plan, st) : launch_fit_t<DT, float>(P, plan, st);
 }
 
 template <int DT>
-int max_grid_dt(const Dense& P, int recur64, int variant) {
-    if (recur64)
-        return variant == 1 ? fit_max_grid<DT, double, 1>(P) : fit_max_grid<DT, double, 2>(P);
-    return variant == 1 ? fit_max_grid<DT, float, 1>(P) : fit_max_grid<DT, float, 2>(P);
+int max_grid_dt(const Dense& P, int recur64) {
+    return recur64 ? fit_max_grid<DT, double>(P) : fit_max_grid<DT, float>(P);
 }
 
-int max_grid(const Dense& P, int dtype, int recur64, int variant) {
+int max_grid(const Dense& P, int dtype, int recur64) {
     switch (dtype) {
-        case DT_F32: return max_grid_dt<DT_F32>(P, recur64, variant);
-        case DT_BF16: return max_grid_dt<DT_BF16>(P, recur64, variant);
-        case DT_F16: return max_grid_dt<DT_F16>(P, recur64, variant);
-        default: return max_grid_dt<DT_FP8>(P, recur64, variant);
+        case DT_F32: return max_grid_dt<DT_F32>(P, recur64);
+        case DT_BF16: return max_grid_dt<DT_BF16>(P, recur64);
+        case DT_F16: return max_grid_dt<DT_F16>(P, recur64);
+        default: return max_grid_dt<DT_FP8>(P, recur64);
     }
 }
 
 }  // namespace
+
+casgd_status run_fit_batch(const Dense* table_dev, const int2* wgmap_dev, int grid, int dtype,
+                           size_t lds, unsigned long long spin, hipStream_t st) {
+    const void* kern = nullptr;
+    switch (dtype) {
+        case DT_F32: kern = reinterpret_cast<const void*>(k_fit_batch<DT_F32>); break;
+        case DT_BF16: kern = reinterpret_cast<const void*>(k_fit_batch<DT_BF16>); break;
+        case DT_F16: kern = reinterpret_cast<const void*>(k_fit_batch<DT_F16>); break;
+        default: kern = reinterpret_cast<const void*>(k_fit_batch<DT_FP8>); break;
+    }
+    void* args[] = {const_cast<Dense**>(&table_dev), const_cast<int2**>(&wgmap_dev), &spin};
+    CASGD_HIP(hipLaunchCooperativeKernel(kern, dim3(grid), dim3(kNT), args, (unsigned)lds, st));
+    return CASGD_OK;
+}
+
+int batch_max_grid(int dtype, size_t lds) {
+    const void* kern = nullptr;
+    switch (dtype) {
+        case DT_F32: kern = reinterpret_cast<const void*>(k_fit_batch<DT_F32>); break;
+        case DT_BF16: kern = reinterpret_cast<const void*>(k_fit_batch<DT_BF16>); break;
+        case DT_F16: kern = reinterpret_cast<const void*>(k_fit_batch<DT_F16>); break;
+        default: kern = reinterpret_cast<const void*>(k_fit_batch<DT_FP8>); break;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kNT, lds) != hipSuccess) return 0;
+    return per_cu * device_cus();
+}
+
+size_t fit_lds(const Dense& P, int dtype, int recur64) {
+    return fit_lds_bytes(P.sb, P.s, recur64 ? 8 : 4, slice_width_of(dtype));
+}
 
 casgd_status run_zero(unsigned* p, int64_t words, hipStream_t st) {
     if (words <= 0) return CASGD_OK;
@@ -354,7 +399,7 @@ casgd_status plan_fit(const Dense& P, int dtype, const casgd_opts* o, int64_t H,
         plan->exec_mode = 2;  // the fused kernel cannot hold this recurrence in LDS
         return CASGD_OK;
     }
-    const int maxg = max_grid(P, dtype, plan->recur64, variant);
+    const int maxg = max_grid(P, dtype, plan->recur64);
     if (maxg <= 0) {
         plan->exec_mode = 2;
         return CASGD_OK;
@@ -380,11 +425,18 @@ casgd_status run_fit(const Dense& P, int dtype, uint64_t h0, int64_t H, const Fi
         // Barrier words start from zero for every fused launch.
         if ((rc = run_zero(P.flags + FLAG_BAR_COUNT, FLAG_WORDS - FLAG_BAR_COUNT, st)) != CASGD_OK)
             return rc;
+        Dense Q = P;
+        Q.h0 = h0;
+        Q.H = H;
+        Q.variant = plan.variant;
+        Q.gsize = plan.grid;
+        Q.recur64 = plan.recur64;
+        Q.tpr = recurrence_tpr(kNT, P.b);
         switch (dtype) {
-            case DT_F32: return dispatch_fit_dt<DT_F32>(P, h0, H, plan, st);
-            case DT_BF16: return dispatch_fit_dt<DT_BF16>(P, h0, H, plan, st);
-            case DT_F16: return dispatch_fit_dt<DT_F16>(P, h0, H, plan, st);
-            default: return dispatch_fit_dt<DT_FP8>(P, h0, H, plan, st);
+            case DT_F32: return dispatch_fit_dt<DT_F32>(Q, plan, st);
+            case DT_BF16: return dispatch_fit_dt<DT_BF16>(Q, plan, st);
+            case DT_F16: return dispatch_fit_dt<DT_F16>(Q, plan, st);
+            default: return dispatch_fit_dt<DT_FP8>(Q, plan, st);
         }
     }
     // Stream-ordered: gather(h0), margin(h0); then per outer: gram(h),

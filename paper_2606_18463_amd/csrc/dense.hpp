@@ -44,6 +44,13 @@ struct Dense {
     float* x_hist;          // snapshots or nullptr
     int64_t* t_hist;        // snapshot clocks or nullptr
     int64_t snap_every;
+    // fused-launch schedule
+    uint64_t h0;            // first outer iteration
+    int64_t H;              // outer iterations
+    int variant;            // 1 redundant recurrence, 2 single recurrence group
+    int gsize;              // workgroups running this problem
+    int recur64;            // FP64 recurrence
+    int tpr;                // threads per row of the recurrence
 };
 
 __device__ __forceinline__ int slot_of(uint64_t h) { return (int)(h % 3ull); }
@@ -265,15 +272,18 @@ __device__ __forceinline__ void gram_item(const Dense& P, float* Gout, uint64_t 
 #pragma unroll
                 for (int c = 0; c < 4; ++c) mfma_q<DT>(Av[a], Bv[c], q, acc[a][c]);
     };
+    // Pairs of K steps with a single loop exit (a second exit would make the
+    // compiler move the accumulators out of and back into AGPRs every step).
+    int64_t k = k0;
     if (k0 < k1) load(A0, B0, k0);
 #pragma unroll 1
-    for (int64_t k = k0; k < k1; k += 2 * KSTEP) {
-        if (k + KSTEP < k1) load(A1, B1, k + KSTEP);
+    for (; k + 2 * KSTEP <= k1; k += 2 * KSTEP) {
+        load(A1, B1, k + KSTEP);
         mma(A0, B0);
-        if (k + KSTEP >= k1) break;
         if (k + 2 * KSTEP < k1) load(A0, B0, k + 2 * KSTEP);
         mma(A1, B1);
     }
+    if (k < k1) mma(A0, B0);
     (void)diag;
 
     // Row scales of the tile's rows (output layout) and columns.
@@ -485,24 +495,35 @@ __device__ __forceinline__ void recurrence(const Dense& P, const float* G, const
                 }
                 const float* grow = G + (int64_t)t * sb;
                 if (vec4) {
-                    const int nv = (j * b) >> 2;    // float4 chunks of the prefix
-                    const float4* g4 = reinterpret_cast<const float4*>(grow);
-                    for (int base = sub; base < nv; base += kRB * TPR) {
-                        float4 g[kRB];
+                    // kBB blocks at a time: a thread owns the 16-byte chunks sub,
+                    // sub+TPR, ... of the group and issues their loads together;
+                    // each chunk lies in one block i and takes its weight
+                    // beta^(j-1-i).
+                    const int cpb = b >> 2;                 // chunks per block row
+                    const bool pow2 = (cpb & (cpb - 1)) == 0;
+                    const int lcpb = 31 - __builtin_clz(cpb);
+                    constexpr int kBB = 4;
+                    for (int i0 = 0; i0 < j; i0 += kBB) {
+                        const int nb = min(kBB, j - i0);
+                        const int nc = nb * cpb;            // chunks in this group
+                        const float4* g4 = reinterpret_cast<const float4*>(grow + i0 * b);
+                        for (int c0 = sub; c0 < nc; c0 += kRB * TPR) {
+                            float4 g[kRB];
 #pragma unroll
-                        for (int k = 0; k < kRB; ++k) {
-                            const int v = base + k * TPR;
-                            g[k] = v < nv ? g4[v] : make_float4(0.f, 0.f, 0.f, 0.f);
-                        }
+                            for (int k = 0; k < kRB; ++k) {
+                                const int cc = c0 + k * TPR;
+                                g[k] = cc < nc ? g4[cc] : make_float4(0.f, 0.f, 0.f, 0.f);
+                            }
 #pragma unroll
-                        for (int k = 0; k < kRB; ++k) {
-                            const int v = base + k * TPR;
-                            if (v < nv) {
-                                const int u = 4 * v;
-                                const ACC* d = dl + u;
-                                const ACC part = (ACC)g[k].x * d[0] + (ACC)g[k].y * d[1] +
-                                                 (ACC)g[k].z * d[2] + (ACC)g[k].w * d[3];
-                                acc += pw[j - 1 - u / b] * part;
+                            for (int k = 0; k < kRB; ++k) {
+                                const int cc = c0 + k * TPR;
+                                if (cc < nc) {
+                                    const int ib = pow2 ? (cc >> lcpb) : cc / cpb;
+                                    const ACC* d = dl + (i0 * b) + 4 * cc;
+                                    const ACC part = (ACC)g[k].x * d[0] + (ACC)g[k].y * d[1] +
+                                                     (ACC)g[k].z * d[2] + (ACC)g[k].w * d[3];
+                                    acc += pw[j - 1 - (i0 + ib)] * part;
+                                }
                             }
                         }
                     }

@@ -59,6 +59,10 @@ casgd_status run_recurrence(const Dense& P, const float* G, const float* rp, uin
                             bool fp64, hipStream_t st);
 casgd_status run_update(const Dense& P, int dtype, const float* c, uint64_t h, hipStream_t st);
 casgd_status run_zero(unsigned* p, int64_t words, hipStream_t st);
+casgd_status run_fit_batch(const Dense* table_dev, const int2* wgmap_dev, int grid, int dtype,
+                           size_t lds, unsigned long long spin, hipStream_t st);
+int batch_max_grid(int dtype, size_t lds);
+size_t fit_lds(const Dense& P, int dtype, int recur64);
 
 int device_cus();
 

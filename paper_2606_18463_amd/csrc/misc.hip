@@ -26,14 +26,16 @@ casgd_status run_sample(uint64_t seed, uint64_t t0, int64_t count, int64_t m, in
 // inv = 448/amax in FP32, codes = e4m3(x * inv).
 __global__ __launch_bounds__(256) void k_quantize(const float* src, int64_t n, int64_t ld_src,
                                                   int dtype, void* dst, int64_t ld_dst,
-                                                  float* row_scale) {
+                                                  float* row_scale, const float* col_scale) {
     const int64_t i = blockIdx.x;
     const float* row = src + i * ld_src;
+    // value of column k: row[k] (times col_scale[k] if given, rounded to FP32)
+    auto val = [&](int64_t k) { return col_scale ? row[k] * col_scale[k] : row[k]; };
     __shared__ float s_red[4];
     float inv = 1.0f, scale = 1.0f;
     if (dtype == DT_FP8) {
         float a = 0.f;
-        for (int64_t k = threadIdx.x; k < n; k += 256) a = fmaxf(a, fabsf(row[k]));
+        for (int64_t k = threadIdx.x; k < n; k += 256) a = fmaxf(a, fabsf(val(k)));
         for (int off = 32; off > 0; off >>= 1) a = fmaxf(a, __shfl_xor(a, off, 64));
         if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = a;
         __syncthreads();
@@ -45,7 +47,7 @@ __global__ __launch_bounds__(256) void k_quantize(const float* src, int64_t n, i
     }
     if (row_scale && threadIdx.x == 0) row_scale[i] = scale;
     for (int64_t k = threadIdx.x; k < ld_dst; k += 256) {
-        const float v = k < n ? row[k] : 0.0f;
+        const float v = k < n ? val(k) : 0.0f;
         switch (dtype) {
             case DT_F32: static_cast<float*>(dst)[i * ld_dst + k] = v; break;
             case DT_BF16:
@@ -63,9 +65,10 @@ __global__ __launch_bounds__(256) void k_quantize(const float* src, int64_t n, i
 }
 
 casgd_status run_quantize(const float* src, int64_t m, int64_t n, int64_t ld_src, int dtype,
-                          void* dst, int64_t ld_dst, float* row_scale, hipStream_t st) {
+                          void* dst, int64_t ld_dst, float* row_scale, const float* col_scale,
+                          hipStream_t st) {
     hipLaunchKernelGGL(k_quantize, dim3((unsigned)m), dim3(256), 0, st, src, n, ld_src, dtype, dst,
-                       ld_dst, row_scale);
+                       ld_dst, row_scale, col_scale);
     CASGD_HIP(hipGetLastError());
     return CASGD_OK;
 }

@@ -1,0 +1,75 @@
+"""Many uneven problems in one fused launch (MI355X): every problem equals its
+own solo fit bit for bit, and the solo fits match the FP64 oracle."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import reference as R  # noqa: E402
+from workloads import uneven_problem, uneven_problem_specs  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def cg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_18463_amd as cg
+    cg._lib.load()
+    return cg
+
+
+def _problems(cg, count, seed, fmt, scale_m=0.1):
+    specs = uneven_problem_specs(count, seed, m_range=(1e4 * scale_m, 2e5 * scale_m),
+                                 n_range=(64, 1024))
+    out = []
+    code = {"f32": cg.F32, "bf16": cg.BF16, "fp8": cg.FP8E4M3}[fmt]
+    for i, sp in enumerate(specs):
+        p = uneven_problem(sp)
+        src = torch.from_numpy(p.X).cuda()
+        stored, scale = cg.casgd_quantize(src, code)
+        X = cg.dense_matrix(stored, scale, n=p.n)
+        _, _, exact = R.quantize(p.X, fmt)
+        b, s = [(16, 4), (32, 8), (8, 1), (64, 16)][i % 4]
+        out.append(dict(p=p, X=X, exact=exact, y=torch.from_numpy(p.y).cuda(), b=b, s=s,
+                        eta=0.5, lam=1e-5, seed=100 + i, H=max(3, 400 // s)))
+    return out
+
+
+@pytest.mark.parametrize("fmt", ["f32", "bf16"])
+def test_batch_equals_solo_and_oracle(cg, fmt):
+    probs = _problems(cg, 7, 5, fmt)
+    xs = [torch.zeros(q["p"].n, device="cuda") for q in probs]
+    batch = [dict(X=q["X"], y=q["y"], x=xs[i], eta=q["eta"], lam=q["lam"], b=q["b"], s=q["s"],
+                  seed=q["seed"], n_outer=q["H"], variant=2 if q["s"] > 1 else 1)
+             for i, q in enumerate(probs)]
+    wss = cg.casgd_fit_batch(batch)
+    for ws in wss:
+        cg.casgd_check(ws)
+    for i, q in enumerate(probs):
+        solo = torch.zeros(q["p"].n, device="cuda")
+        o = cg.opts(fused_variant=batch[i]["variant"])
+        cg.casgd_fit(q["X"], q["y"], solo, q["eta"], q["lam"], q["b"], q["s"], q["seed"], 0,
+                     q["H"], opts=o)
+        assert torch.equal(solo, xs[i]), i
+        xo = R.casgd(q["exact"], q["p"].y, np.zeros(q["p"].n), q["eta"], q["lam"], q["b"],
+                     q["s"], q["seed"], 0, q["H"])
+        xg = xs[i].cpu().numpy().astype(np.float64)
+        assert np.linalg.norm(xg - xo) / max(np.linalg.norm(xo), 1e-30) < 1e-4, i
+
+
+def test_batch_explicit_groups(cg):
+    probs = _problems(cg, 3, 9, "f32")
+    xs = [torch.zeros(q["p"].n, device="cuda") for q in probs]
+    batch = [dict(X=q["X"], y=q["y"], x=xs[i], eta=q["eta"], lam=q["lam"], b=q["b"], s=q["s"],
+                  seed=q["seed"], n_outer=q["H"], groups=3, variant=2 if q["s"] > 1 else 1)
+             for i, q in enumerate(probs)]
+    for ws in cg.casgd_fit_batch(batch):
+        cg.casgd_check(ws)
+    for i, q in enumerate(probs):
+        solo = torch.zeros(q["p"].n, device="cuda")
+        o = cg.opts(fused_variant=batch[i]["variant"])
+        cg.casgd_fit(q["X"], q["y"], solo, q["eta"], q["lam"], q["b"], q["s"], q["seed"], 0,
+                     q["H"], opts=o)
+        assert torch.equal(solo, xs[i]), i
