@@ -315,10 +315,23 @@ casgd_status casgd_quantize_scaled(const float *src, int64_t m, int64_t n, int64
 casgd_status casgd_mlp_features(const float *stats, int64_t N, const float *norm, float *feats,
                                 void *stream);
 
+/* Feature normalisation over N training rows (device): norm[c] = mean_k
+ * log(1 + |stats[k][c]|), norm[4 + c] = max(sample standard deviation, 1e-6),
+ * c = 0..3, accumulated in FP64 in a fixed order. N >= 1. */
+casgd_status casgd_mlp_feature_norm(const float *stats, int64_t N, float *norm, void *stream);
+
 /* out (device, N x 2); pre (device, N x 64, the hidden pre-activations kept
  * for the backward pass) may be NULL. */
 casgd_status casgd_mlp_forward(const float *params, const float *feats, int64_t N, float *out,
                                float *pre, void *stream);
+
+/* Applies a forward output (device, N x 2) for one problem of N columns: the
+ * step scale d_k = exp(clamp(out[k][0] - mean_j out[j][0], -20, 20)) is
+ * returned as the column scale q_k = sqrt(d_k) (device, N), and
+ * eta[0] = exp(mean_j out[j][1]) (device, 1 float). N >= 1. The scaled problem
+ * X~ = X diag(q) is built with casgd_quantize_scaled; a fit of X~ gives x~ and
+ * x = q * x~ (X~ x~ = X x, so losses of x~ on X~ equal those of x on X). */
+casgd_status casgd_mlp_apply(const float *out, int64_t N, float *q, float *eta, void *stream);
 
 /* Workspace of casgd_mlp_loss_grad / casgd_mlp_backward for N rows, P problems. */
 size_t casgd_mlp_workspace_size(int64_t N, int32_t P);
@@ -351,6 +364,13 @@ casgd_status casgd_adam_step(float *params, const float *grad, float *m1, float 
 size_t casgd_hess_diag_workspace_size(const casgd_matrix *X);
 casgd_status casgd_hess_diag(const casgd_matrix *X, const float *x, double lambda, float *hdiag,
                              void *ws, size_t ws_bytes, void *stream);
+
+/* Training target of the per-feature scale from a Hessian diagonal h (device,
+ * n, positive): t_d = -log h_k + mean_j log h_j (device, n), the log of a
+ * Jacobi preconditioner normalised to unit geometric mean, and, when q is not
+ * NULL, the column scale q = exp(t_d / 2) (device, n). n >= 1. */
+casgd_status casgd_jacobi_target(const float *hdiag, int64_t n, float *t_d, float *q,
+                                 void *stream);
 
 /* --------------------------------------------------- measurement support */
 

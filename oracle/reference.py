@@ -497,6 +497,40 @@ def column_stats_csr(row_ptr, col_idx, values, m: int, n: int) -> np.ndarray:
     return np.stack([mean, var, cnt / m, amax], axis=1)
 
 
+# ------------------------------------- learned preconditioner: targets and use
+
+def hess_diag(X, x, lam: float) -> np.ndarray:
+    """Diagonal of the Hessian of the mean logistic loss (Sec. 2.1) plus the L2
+    term at x: m^-1 sum_i s(z_i)(1 - s(z_i)) X_ik^2 + lam, z_i = X_i . x."""
+    X = _f64(X)
+    z = X @ _f64(x)
+    s = 1.0 / (1.0 + np.exp(-z))
+    return (s * (1.0 - s)) @ (X * X) / X.shape[0] + lam
+
+
+def jacobi_target(h) -> tuple:
+    """(t_d, q): t_d = -log h centred to zero mean (log of a Jacobi scale with
+    unit geometric mean) and the column scale q = exp(t_d / 2)."""
+    t = -np.log(_f64(h))
+    t = t - t.mean()
+    return t, np.exp(0.5 * t)
+
+
+def feature_norm(stats) -> tuple:
+    """(mu, sd) of log(1 + |stat|) per statistic over all rows; sample std,
+    floored at 1e-6."""
+    L = np.log1p(np.abs(_f64(stats)))
+    return L.mean(axis=0), np.maximum(L.std(axis=0, ddof=1), 1e-6)
+
+
+def mlp_apply(o) -> tuple:
+    """(q, eta) for one problem from its forward output o (N x 2):
+    q = exp(clip(o0 - mean o0, -20, 20) / 2), eta = exp(mean o1)."""
+    o = _f64(o)
+    t = np.clip(o[:, 0] - o[:, 0].mean(), -20.0, 20.0)
+    return np.exp(0.5 * t), float(np.exp(o[:, 1].mean()))
+
+
 # ------------------------------------------------------- MLP (FP64 reference)
 
 def mlp_features(stats: np.ndarray, mu: np.ndarray, sd: np.ndarray) -> np.ndarray:

@@ -301,6 +301,35 @@ def casgd_mlp_features(stats, norm, stream=None):
     return feats
 
 
+def casgd_mlp_feature_norm(stats, stream=None):
+    """(8,) device FP32: means then standard deviations of log(1 + |stats|)."""
+    torch = _torch()
+    norm = torch.empty(8, dtype=torch.float32, device=stats.device)
+    _check(_L().casgd_mlp_feature_norm(_ptr(stats), stats.shape[0], _ptr(norm), _stream(stream)))
+    return norm
+
+
+def casgd_mlp_apply(out, stream=None):
+    """(q, eta) from a forward output of one problem: column scale q = sqrt(d) (N,)
+    and step size eta (1,), device FP32."""
+    torch = _torch()
+    N = out.shape[0]
+    q = torch.empty(N, dtype=torch.float32, device=out.device)
+    eta = torch.empty(1, dtype=torch.float32, device=out.device)
+    _check(_L().casgd_mlp_apply(_ptr(out), N, _ptr(q), _ptr(eta), _stream(stream)))
+    return q, eta
+
+
+def casgd_jacobi_target(hdiag, want_q: bool = True, stream=None):
+    """(t_d, q or None): centred -log of a Hessian diagonal and exp(t_d / 2)."""
+    torch = _torch()
+    n = hdiag.numel()
+    t_d = torch.empty(n, dtype=torch.float32, device=hdiag.device)
+    q = torch.empty(n, dtype=torch.float32, device=hdiag.device) if want_q else None
+    _check(_L().casgd_jacobi_target(_ptr(hdiag), n, _ptr(t_d), _ptr(q), _stream(stream)))
+    return t_d, q
+
+
 def casgd_mlp_forward(params, feats, want_pre: bool = True, stream=None):
     torch = _torch()
     N = feats.shape[0]

@@ -73,6 +73,9 @@ SIGNATURES = {
     "casgd_quantize_scaled": (c_i32, [c_vp, c_i64, c_i64, c_i64, c_vp, c_i32, c_vp, c_i64, c_vp,
                                       c_vp]),
     "casgd_mlp_features": (c_i32, [c_vp, c_i64, c_vp, c_vp, c_vp]),
+    "casgd_mlp_feature_norm": (c_i32, [c_vp, c_i64, c_vp, c_vp]),
+    "casgd_mlp_apply": (c_i32, [c_vp, c_i64, c_vp, c_vp, c_vp]),
+    "casgd_jacobi_target": (c_i32, [c_vp, c_i64, c_vp, c_vp, c_vp]),
     "casgd_mlp_forward": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp, c_vp]),
     "casgd_mlp_workspace_size": (c_sz, [c_i64, c_i32]),
     "casgd_mlp_loss_grad": (c_i32, [c_vp, c_vp, c_i32, c_i64, c_vp, c_vp, ctypes.c_float, c_vp,

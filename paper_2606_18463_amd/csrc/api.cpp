@@ -708,6 +708,31 @@ casgd_status casgd_adam_step(float* params, const float* grad, float* m1, float*
     return run_adam(params, grad, m1, m2, count, t, lr, beta1, beta2, eps, (hipStream_t)stream);
 }
 
+casgd_status casgd_mlp_feature_norm(const float* stats, int64_t N, float* norm, void* stream) {
+    if (N < 1 || !stats || !norm) {
+        set_error("bad arguments to casgd_mlp_feature_norm");
+        return CASGD_EINVAL;
+    }
+    return run_feature_norm(stats, N, norm, (hipStream_t)stream);
+}
+
+casgd_status casgd_mlp_apply(const float* out, int64_t N, float* q, float* eta, void* stream) {
+    if (N < 1 || !out || !q || !eta) {
+        set_error("bad arguments to casgd_mlp_apply");
+        return CASGD_EINVAL;
+    }
+    return run_mlp_apply(out, N, q, eta, (hipStream_t)stream);
+}
+
+casgd_status casgd_jacobi_target(const float* hdiag, int64_t n, float* t_d, float* q,
+                                 void* stream) {
+    if (n < 1 || !hdiag || !t_d) {
+        set_error("bad arguments to casgd_jacobi_target");
+        return CASGD_EINVAL;
+    }
+    return run_jacobi_target(hdiag, n, t_d, q, (hipStream_t)stream);
+}
+
 size_t casgd_hess_diag_workspace_size(const casgd_matrix* X) {
     return X ? hess_ws(X) : 0;
 }

@@ -33,6 +33,9 @@ casgd_status run_mlp_backward(const float* params, const float* feats, const flo
                               hipStream_t st);
 casgd_status run_adam(float* p, const float* g, float* m1, float* m2, int count, int64_t t,
                       float lr, float b1, float b2, float eps, hipStream_t st);
+casgd_status run_feature_norm(const float* stats, int64_t N, float* norm, hipStream_t st);
+casgd_status run_mlp_apply(const float* out, int64_t N, float* q, float* eta, hipStream_t st);
+casgd_status run_jacobi_target(const float* h, int64_t n, float* t_d, float* q, hipStream_t st);
 size_t hess_ws(const casgd_matrix* X);
 casgd_status run_hess_diag(const casgd_matrix* X, const float* x, double lambda, float* hdiag,
                            void* ws, hipStream_t st);

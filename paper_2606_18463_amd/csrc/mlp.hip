@@ -236,6 +236,77 @@ __global__ void k_hess_final(const double* partial, int nrb, int64_t m, int64_t 
     hdiag[k] = (float)(a / (double)m + lambda);
 }
 
+// ------------------------------------------- single-workgroup reductions
+// The per-problem post-processing below reduces over at most a few hundred
+// thousand values, so one 1024-thread workgroup does it: every thread sums a
+// fixed stride in FP64, then a fixed-shape tree over LDS.
+constexpr int kRedThreads = 1024;
+
+__device__ double block_sum_f64(double v, double* lds) {
+    lds[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) lds[threadIdx.x] += lds[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double r = lds[0];
+    __syncthreads();
+    return r;
+}
+
+// norm[c] = mean_k log(1 + |stats[k][c]|), norm[4 + c] = max(sample std, 1e-6).
+__global__ __launch_bounds__(kRedThreads) void k_feature_norm(const float* stats, int64_t N,
+                                                               float* norm) {
+    __shared__ double lds[kRedThreads];
+    for (int c = 0; c < kIn; ++c) {
+        double a = 0.0;
+        for (int64_t k = threadIdx.x; k < N; k += kRedThreads)
+            a += log1p(fabs((double)stats[k * kIn + c]));
+        const double mu = block_sum_f64(a, lds) / (double)N;
+        double q = 0.0;
+        for (int64_t k = threadIdx.x; k < N; k += kRedThreads) {
+            const double v = log1p(fabs((double)stats[k * kIn + c])) - mu;
+            q += v * v;
+        }
+        const double var = block_sum_f64(q, lds) / (double)(N > 1 ? N - 1 : 1);
+        if (threadIdx.x == 0) {
+            norm[c] = (float)mu;
+            norm[kIn + c] = (float)fmax(sqrt(var), 1e-6);
+        }
+    }
+}
+
+// q_k = exp(clamp(out[k][0] - mean_k out[k][0], -20, 20) / 2), the column scale
+// sqrt(d_k); eta = exp(mean_k out[k][1]).
+__global__ __launch_bounds__(kRedThreads) void k_mlp_apply(const float* out, int64_t N, float* q,
+                                                            float* eta) {
+    __shared__ double lds[kRedThreads];
+    double a0 = 0.0, a1 = 0.0;
+    for (int64_t k = threadIdx.x; k < N; k += kRedThreads) {
+        a0 += (double)out[k * kOut];
+        a1 += (double)out[k * kOut + 1];
+    }
+    const double mu0 = block_sum_f64(a0, lds) / (double)N;
+    const double mu1 = block_sum_f64(a1, lds) / (double)N;
+    for (int64_t k = threadIdx.x; k < N; k += kRedThreads)
+        q[k] = (float)exp(0.5 * fmin(fmax((double)out[k * kOut] - mu0, -20.0), 20.0));
+    if (threadIdx.x == 0) eta[0] = (float)exp(mu1);
+}
+
+// t_d = -log h + mean_k log h_k (centred); q = exp(t_d / 2) when q is not null.
+__global__ __launch_bounds__(kRedThreads) void k_jacobi_target(const float* h, int64_t n,
+                                                                float* t_d, float* q) {
+    __shared__ double lds[kRedThreads];
+    double a = 0.0;
+    for (int64_t k = threadIdx.x; k < n; k += kRedThreads) a += log((double)h[k]);
+    const double mu = block_sum_f64(a, lds) / (double)n;
+    for (int64_t k = threadIdx.x; k < n; k += kRedThreads) {
+        const double t = mu - log((double)h[k]);
+        t_d[k] = (float)t;
+        if (q) q[k] = (float)exp(0.5 * t);
+    }
+}
+
 // ------------------------------------------------------------------ host
 
 casgd_status run_mlp_features(const float* stats, int64_t N, const float* norm, float* feats,
@@ -340,6 +411,24 @@ casgd_status run_hess_diag(const casgd_matrix* X, const float* x, double lambda,
     CASGD_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_hess_final, dim3((unsigned)((X->n + 255) / 256)), dim3(256), 0, st,
                        partial, kStatRowBlocks, X->m, X->n, lambda, hdiag);
+    CASGD_HIP(hipGetLastError());
+    return CASGD_OK;
+}
+
+casgd_status run_feature_norm(const float* stats, int64_t N, float* norm, hipStream_t st) {
+    hipLaunchKernelGGL(k_feature_norm, dim3(1), dim3(kRedThreads), 0, st, stats, N, norm);
+    CASGD_HIP(hipGetLastError());
+    return CASGD_OK;
+}
+
+casgd_status run_mlp_apply(const float* out, int64_t N, float* q, float* eta, hipStream_t st) {
+    hipLaunchKernelGGL(k_mlp_apply, dim3(1), dim3(kRedThreads), 0, st, out, N, q, eta);
+    CASGD_HIP(hipGetLastError());
+    return CASGD_OK;
+}
+
+casgd_status run_jacobi_target(const float* h, int64_t n, float* t_d, float* q, hipStream_t st) {
+    hipLaunchKernelGGL(k_jacobi_target, dim3(1), dim3(kRedThreads), 0, st, h, n, t_d, q);
     CASGD_HIP(hipGetLastError());
     return CASGD_OK;
 }

@@ -86,7 +86,27 @@ def test_hess_diag_and_scaled_quantize(cg, fmt):
     _, _, exact = R.quantize(scaled, fmt)
     x = (np.random.default_rng(2).standard_normal(300) * 0.3).astype(np.float32)
     h = cg.casgd_hess_diag(Xs, _dev(x), 1e-3).cpu().numpy()
-    z = exact @ x.astype(np.float64)
-    sg = 1 / (1 + np.exp(-z))
-    ref = (sg * (1 - sg)) @ (exact ** 2) / exact.shape[0] + 1e-3
+    ref = R.hess_diag(exact, x, 1e-3)
     assert np.allclose(h, ref, rtol=1e-4)
+
+
+def test_feature_norm_apply_and_jacobi_target_vs_oracle(cg):
+    g = np.random.default_rng(4)
+    st = (np.abs(g.standard_normal((3000, 4))) * [1, 10, 0.1, 3]).astype(np.float32)
+    norm = cg.casgd_mlp_feature_norm(_dev(st)).cpu().numpy()
+    mu, sd = R.feature_norm(st)
+    assert np.allclose(norm[:4], mu, rtol=1e-6, atol=1e-7)
+    assert np.allclose(norm[4:], sd, rtol=1e-6)
+
+    o = (g.standard_normal((2500, 2)) * [3.0, 0.5]).astype(np.float32)
+    o[7, 0] = 60.0   # clipped
+    q, eta = cg.casgd_mlp_apply(_dev(o))
+    rq, reta = R.mlp_apply(o)
+    assert np.allclose(q.cpu().numpy(), rq, rtol=1e-6)
+    assert np.isclose(float(eta), reta, rtol=1e-6)
+
+    h = np.exp(g.uniform(-5, 5, 2049)).astype(np.float32)
+    t_d, q = cg.casgd_jacobi_target(_dev(h))
+    rt, rq = R.jacobi_target(h)
+    assert np.allclose(t_d.cpu().numpy(), rt, atol=2e-6)
+    assert np.allclose(q.cpu().numpy(), rq, rtol=2e-6)

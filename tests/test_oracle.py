@@ -355,6 +355,51 @@ def test_mlp_gradients_match_finite_differences():
             assert abs(fd - gp.reshape(-1)[k]) < 1e-6 * max(1.0, abs(fd)), (pi, k)
 
 
+def test_hess_diag_matches_second_differences_of_objective():
+    # H_kk is the second derivative of F_lambda along coordinate k; the
+    # objective is a separate code path (stable softplus, no sigmoid).
+    g = np.random.default_rng(7)
+    X = g.standard_normal((200, 6))
+    y = np.where(g.random(200) < 0.5, -1.0, 1.0)
+    x = g.standard_normal(6) * 0.4
+    lam = 1e-2
+    h = R.hess_diag(X * y[:, None], x, lam)  # sign of the label cancels in s(1-s) X^2
+    assert np.allclose(h, R.hess_diag(X, x, lam), rtol=1e-13)
+    e = 1e-4
+    for k in range(6):
+        u = np.zeros(6)
+        u[k] = e
+        fd = (R.objective(X, y, x + u, lam) - 2 * R.objective(X, y, x, lam)
+              + R.objective(X, y, x - u, lam)) / e ** 2
+        assert abs(fd - h[k]) < 1e-6 * max(1.0, h[k]), k
+
+
+def test_jacobi_target_unit_geometric_mean_and_scale():
+    h = np.array([4.0, 1.0, 0.25, 16.0])
+    t, q = R.jacobi_target(h)
+    assert abs(t.sum()) < 1e-14
+    # q^2 h is constant: the scaled Hessian diagonal is uniform
+    assert np.allclose(q * q * h, (q * q * h)[0], rtol=1e-14)
+    assert np.allclose(np.exp(t.mean()), 1.0)
+
+
+def test_feature_norm_standardises_features():
+    st = np.abs(np.random.default_rng(8).standard_normal((500, 4))) * [1, 10, 0.1, 3]
+    mu, sd = R.feature_norm(st)
+    F = R.mlp_features(st, mu, sd)
+    assert np.allclose(F.mean(axis=0), 0.0, atol=1e-12)
+    assert np.allclose(F.std(axis=0, ddof=1), 1.0, rtol=1e-12)
+    const = np.ones((10, 4))
+    assert np.all(R.feature_norm(const)[1] == 1e-6)
+
+
+def test_mlp_apply_centres_and_clips():
+    o = np.array([[1.0, 0.0], [3.0, np.log(4.0)], [50.0, np.log(0.25)], [-40.0, 0.0]])
+    q, eta = R.mlp_apply(o)
+    assert np.allclose(np.log(q) * 2, [-2.5, -0.5, 20.0, -20.0])
+    assert np.isclose(eta, 1.0)
+
+
 def test_adam_first_step_is_signed_lr():
     p = np.array([1.0, -2.0, 3.0])
     g = np.array([0.5, -4.0, 1e-3])
