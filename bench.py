@@ -258,12 +258,14 @@ def main():
     if args.sweep:
         rows = []
         for ss in (1, 4, 16, 32):
-            Ks = max(8, (1 << 16) // ss)
-            mss, _, _ = timed_fit(cg, X, y, n, b, ss, ETA_C2, LAMBDA_C2, Ks, max(2, Ks // 20),
-                                  dict(exec_mode=args.exec_mode))
-            rows.append({"s": ss, "updates_per_s": round(ss * Ks / (mss * 1e-3), 1),
-                         "us_per_outer": round(mss * 1e3 / Ks, 3)})
-            log(f"[sweep] s={ss}: {rows[-1]}")
+            for em in (1, 2):
+                Ks = max(8, (1 << 15) // ss)
+                mss, _, _ = timed_fit(cg, X, y, n, b, ss, ETA_C2, LAMBDA_C2, Ks, max(2, Ks // 20),
+                                      dict(exec_mode=em))
+                rows.append({"s": ss, "exec_mode": em,
+                             "updates_per_s": round(ss * Ks / (mss * 1e-3), 1),
+                             "us_per_outer": round(mss * 1e3 / Ks, 3)})
+                log(f"[sweep] {rows[-1]}")
         out["sweep"] = rows
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, b, s, ETA_C2, LAMBDA_C2)

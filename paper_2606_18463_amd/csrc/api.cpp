@@ -70,19 +70,32 @@ bool dense_layout(int64_t n, int dtype, int b, int s, DenseLayout* L) {
             if ((TI * kTile) / b < rlast / b) ++needed;
         }
     L->needed = needed;
+    L->bt = (b % kTile == 0) ? b / kTile : 0;
+    L->gt = L->bt > 0 ? needed : L->ntiles;
     const int kstep = 4 * dtype_vec(dtype);
     const int64_t kpad = (n + kstep - 1) / kstep * kstep;
-    L->ldy = (n + 127) / 128 * 128;
+    // Row strides with a 256-byte pad: rows of the gathered block and of G are
+    // read many at a time, and a power-of-two stride would put all of them on
+    // one memory channel.
+    L->ldy = (n + 127) / 128 * 128 + 256 / dtype_bytes(dtype);
+    L->ldg = sb + 64;
+    // Gram units: whole 64x64 tiles, or half tiles when there are fewer tiles
+    // than compute units. K splits across workgroups (a power of two that
+    // divides the eight XCDs) only for very small Gram matrices (units fill
+    // less than a quarter of the chip), and while every wave keeps at least
+    // max(128, 4 K steps) of K: the split-K handshake costs a cache
+    // write-back per workgroup.
+    const int ncu = device_cus();
+    L->gna = L->gt < ncu ? 2 : 4;
+    const int units = L->gna == 4 ? L->gt : 2 * L->gt;
+    const int64_t kmin = std::max<int64_t>(128, 4 * kstep);
     int ksplit = 1;
-    if (s > 1 && needed > 0) {
-        const int target = 2048;  // waves: about two per SIMD of the chip
-        const int kmax = (int)std::max<int64_t>(1, n / 256);
-        ksplit = std::max(1, std::min(target / needed, kmax));
-    }
+    if (s > 1 && needed > 0)
+        while (ksplit < 8 && 4 * units * ksplit < ncu && kpad / (2 * ksplit * 4) >= kmin)
+            ksplit *= 2;
     int64_t kchunk = (kpad + ksplit - 1) / ksplit;
     kchunk = (kchunk + kstep - 1) / kstep * kstep;
-    ksplit = (int)((kpad + kchunk - 1) / kchunk);
-    L->ksplit = std::max(1, ksplit);
+    L->ksplit = ksplit;
     L->kchunk = kchunk;
     const int kw = slice_width_of(dtype);
     L->nslices = (int)((n + kw - 1) / kw);
@@ -91,8 +104,8 @@ bool dense_layout(int64_t n, int dtype, int b, int s, DenseLayout* L) {
     L->off_flags = off;
     off = align256(off + FLAG_WORDS * 4);
     L->off_tilecnt = off;
-    off = align256(off + (size_t)L->ntiles * 4);
-    const size_t gbytes = s > 1 ? (size_t)sb * sb * 4 : 0;
+    off = align256(off + (size_t)L->ntiles * 2 * 4);
+    const size_t gbytes = s > 1 ? (size_t)sb * L->ldg * 4 : 0;
     L->off_G0 = off;
     off = align256(off + gbytes);
     L->off_G1 = off;
@@ -125,6 +138,9 @@ void dense_bind(const DenseLayout& L, void* ws, Dense* P) {
     P->sb = L.sb;
     P->ts = L.ts;
     P->ntiles = L.ntiles;
+    P->gt = L.gt;
+    P->bt = L.bt;
+    P->gna = L.gna;
     P->ksplit = L.ksplit;
     P->kchunk = L.kchunk;
     P->nslices = L.nslices;
@@ -137,6 +153,7 @@ void dense_bind(const DenseLayout& L, void* ws, Dense* P) {
     P->rp[1] = reinterpret_cast<float*>(w + L.off_rp1);
     P->c = reinterpret_cast<float*>(w + L.off_c);
     P->ldy = L.ldy;
+    P->ldg = L.ldg;
     for (int k = 0; k < 3; ++k) {
         P->Y[k] = w + L.off_Y[k];
         P->yI[k] = reinterpret_cast<float*>(w + L.off_yI[k]);
@@ -528,7 +545,7 @@ casgd_status casgd_fit_batch(const casgd_problem* probs, int32_t count, int64_t 
     }
     const int grid = (int)wgmap.size();
     for (int i = 0; i < count; ++i) {
-        if ((rc = run_zero(D[i].tile_cnt, D[i].ntiles, st)) != CASGD_OK) return rc;
+        if ((rc = run_zero(D[i].tile_cnt, 2 * D[i].ntiles, st)) != CASGD_OK) return rc;
         if ((rc = run_zero(D[i].flags + FLAG_BAR_COUNT, FLAG_WORDS - FLAG_BAR_COUNT, st)) != CASGD_OK)
             return rc;
     }
@@ -564,8 +581,9 @@ casgd_status casgd_gram_margin(const casgd_matrix* X, const float* x, int32_t b,
     casgd_status rc = make_dense(X, nullptr, const_cast<float*>(x), 1.0, 0.0, b, s, seed, nullptr,
                                  ws, ws_bytes, &P, &L, true);
     if (rc != CASGD_OK) return rc;
+    P.ldg = P.sb;   // the caller's G is sb x sb
     hipStream_t st = (hipStream_t)stream;
-    if ((rc = run_zero(P.tile_cnt, P.ntiles, st)) != CASGD_OK) return rc;
+    if ((rc = run_zero(P.tile_cnt, 2 * P.ntiles, st)) != CASGD_OK) return rc;
     if ((rc = run_gather(P, X->dtype, outer_iter, st)) != CASGD_OK) return rc;
     if ((rc = run_gram(P, X->dtype, G, outer_iter, st)) != CASGD_OK) return rc;
     if (!x) return CASGD_OK;
@@ -592,6 +610,7 @@ casgd_status casgd_recurrence(const float* G, const float* r, const float* yI, i
     P.b = b;
     P.s = s;
     P.sb = b * s;
+    P.ldg = P.sb;
     P.alpha_d = eta / b;
     P.beta_d = 1.0 - eta * lambda;
     P.alpha = (float)P.alpha_d;

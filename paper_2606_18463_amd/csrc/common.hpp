@@ -156,6 +156,12 @@ __device__ __forceinline__ unsigned atomic_load_relaxed(unsigned* p) {
 __device__ __forceinline__ void atomic_store_release(unsigned* p, unsigned v) {
     __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ void fence_acquire_agent() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+__device__ __forceinline__ void fence_release_agent() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+}
 __device__ __forceinline__ void atomic_store_relaxed(unsigned* p, unsigned v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -176,26 +182,32 @@ __device__ __forceinline__ void raise_flag(unsigned* flags, int which) {
 
 // Grid-wide barrier for a launch whose workgroups are all resident (the
 // cooperative launch guarantees it). Sense is kept in a generation counter.
+// One thread per workgroup synchronises for the whole workgroup (after a
+// workgroup barrier, its agent-scope release and acquire cover every wave):
+// agent-scope release and acquire write back and invalidate the XCD's L2, so
+// they are issued once per workgroup, and the poll itself uses relaxed loads
+// (which read the coherent copy without touching the caches).
 // The wait is bounded: after `spin_limit` polls the timeout flag is raised
 // and every workgroup leaves the barrier (and then the kernel) at once, so a
 // launch can never wait forever. Returns false when the kernel must stop.
 __device__ __forceinline__ bool grid_barrier(unsigned* flags, unsigned nblocks,
                                              unsigned long long spin_limit) {
     __shared__ int s_stop;
-    __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned* count = flags + FLAG_BAR_COUNT;
         unsigned* gen = flags + FLAG_BAR_GEN;
         const unsigned g = atomic_load_relaxed(gen);
-        const unsigned arrived = atomic_add_acq_rel(count, 1u);
+        const unsigned arrived =
+            __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         int stop = 0;
         if (arrived == nblocks - 1) {
+            fence_acquire_agent();
             atomic_store_relaxed(count, 0u);
             atomic_store_release(gen, g + 1u);
         } else {
             unsigned long long spins = 0;
-            while (atomic_load_acquire(gen) == g) {
+            while (atomic_load_relaxed(gen) == g) {
                 if (++spins > spin_limit) {
                     raise_flag(flags, FLAG_TIMEOUT);
                     stop = 1;
@@ -207,12 +219,12 @@ __device__ __forceinline__ bool grid_barrier(unsigned* flags, unsigned nblocks,
                 }
                 __builtin_amdgcn_s_sleep(1);
             }
+            fence_acquire_agent();
         }
         if (atomic_load_relaxed(flags + FLAG_TIMEOUT)) stop = 1;
         s_stop = stop;
     }
     __syncthreads();
-    __threadfence();
     return s_stop == 0;
 }
 

@@ -30,10 +30,9 @@ __global__ __launch_bounds__(kNT) void k_gather(Dense P, uint64_t h) {
 }
 
 template <int DT>
-__global__ __launch_bounds__(kNT) void k_gram(Dense P, float* Gout, uint64_t h, int nitems) {
-    const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * kNW + (threadIdx.x >> 6));
-    if (item >= nitems) return;
-    gram_item<DT>(P, Gout, h, item);
+__global__ __launch_bounds__(kNT) void k_gram(Dense P, float* Gout, uint64_t h) {
+    __shared__ __align__(16) unsigned char lds[kGramLds];
+    gram_phase<DT>(P, Gout, h, 0, gridDim.x, lds);
 }
 
 template <int DT>
@@ -75,7 +74,8 @@ __host__ __device__ inline size_t fit_lds_bytes(int sb, int s, int acc_bytes, in
     off = (off + 15) & ~(size_t)15;
     off += (size_t)sb * 4;                // c copy
     off += (size_t)kNW * kw * 4 + kw * 4; // red + xs
-    return off;
+    // the Gram phase reuses the same memory (phases never overlap in a workgroup)
+    return s > 1 && off < kGramLds ? kGramLds : off;
 }
 
 // One problem's whole fit on the workgroups wg = 0 .. nb-1 of its group (the
@@ -93,8 +93,10 @@ __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigne
     float* xs = red + kNW * KW;
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int nitems = P.ntiles * P.ksplit;
     const bool has_gram = P.s > 1;
+    // physical workgroup range of this problem (the Gram phase maps K splits
+    // to XCDs by physical index)
+    const int base = (int)blockIdx.x - wg;
     const uint64_t h0 = P.h0;
     const int64_t H = P.H;
     const int tpr = P.tpr;
@@ -107,8 +109,7 @@ __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigne
     gather_rows<DT>(P, h0, gw, ngw);
     if (H > 1) gather_rows<DT>(P, h0 + 1, gw, ngw);
     if (!grid_barrier(P.flags, nb, spin)) return;
-    if (has_gram)
-        for (int it = gw; it < nitems; it += ngw) gram_item<DT>(P, P.G[0], h0, it);
+    if (has_gram) gram_phase<DT>(P, P.G[0], h0, base, base + nb, lds);
     for (int sl = wg; sl < P.nslices; sl += nb)
         update_margin_slice<DT, kNW>(P, sl, nullptr, 0, false, h0, true, P.rp[0], red, xs, -1);
     if (!grid_barrier(P.flags, nb, spin)) return;
@@ -128,9 +129,7 @@ __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigne
                     update_margin_slice<DT, kNW>(P, sl, cl, h, true, h + 1, more, pick2(P.rp, nxt),
                                                  red, xs, snap_row);
             }
-            if (has_gram && more)
-                for (int it = gw; it < nitems; it += ngw)
-                    gram_item<DT>(P, pick2(P.G, nxt), h + 1, it);
+            if (has_gram && more) gram_phase<DT>(P, pick2(P.G, nxt), h + 1, base, base + nb, lds);
             if (more2) gather_rows<DT>(P, h + 2, gw, ngw);
             if (!grid_barrier(P.flags, nb, spin)) return;
         } else {
@@ -140,8 +139,7 @@ __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigne
             } else {
                 const int gw1 = gw - kNW, ngw1 = ngw - kNW;
                 if (has_gram && more)
-                    for (int it = gw1; it < nitems; it += ngw1)
-                        gram_item<DT>(P, pick2(P.G, nxt), h + 1, it);
+                    gram_phase<DT>(P, pick2(P.G, nxt), h + 1, base + 1, base + nb, lds);
                 if (more2) gather_rows<DT>(P, h + 2, gw1, ngw1);
             }
             if (!grid_barrier(P.flags, nb, spin)) return;
@@ -191,10 +189,9 @@ casgd_status launch_gather_t(const Dense& P, uint64_t h, hipStream_t st) {
 
 template <int DT>
 casgd_status launch_gram_t(const Dense& P, float* Gout, uint64_t h, hipStream_t st) {
-    const int nitems = P.ntiles * P.ksplit;
-    if (nitems == 0 || P.s < 2) return CASGD_OK;
-    const int grid = (nitems + kNW - 1) / kNW;
-    hipLaunchKernelGGL(k_gram<DT>, dim3(grid), dim3(kNT), 0, st, P, Gout, h, nitems);
+    if (P.gt == 0 || P.s < 2) return CASGD_OK;
+    const int grid = (P.gna == 4 ? P.gt : 2 * P.gt) * P.ksplit;
+    hipLaunchKernelGGL(k_gram<DT>, dim3(grid), dim3(kNT), 0, st, P, Gout, h);
     CASGD_HIP(hipGetLastError());
     return CASGD_OK;
 }
@@ -404,8 +401,8 @@ casgd_status plan_fit(const Dense& P, int dtype, const casgd_opts* o, int64_t H,
         plan->exec_mode = 2;
         return CASGD_OK;
     }
-    const int nitems = P.s > 1 ? P.ntiles * P.ksplit : 0;
-    int want = std::max(P.nslices, (nitems + kNW - 1) / kNW + (variant == 2 ? 1 : 0));
+    const int units = P.s > 1 ? (P.gt + kNW - 1) / kNW * P.ksplit : 0;
+    int want = std::max(P.nslices, units + (variant == 2 ? 1 : 0));
     want = std::max(want, variant == 2 ? 2 : 1);
     if (o && o->grid_blocks > 0) want = o->grid_blocks;
     plan->grid = std::min(want, maxg);
@@ -420,7 +417,7 @@ casgd_status run_fit(const Dense& P, int dtype, uint64_t h0, int64_t H, const Fi
     casgd_status rc;
     // Split-K counters must start at zero (they reset themselves after use,
     // but a launch that stopped early may leave them set).
-    if ((rc = run_zero(P.tile_cnt, P.ntiles, st)) != CASGD_OK) return rc;
+    if ((rc = run_zero(P.tile_cnt, 2 * P.ntiles, st)) != CASGD_OK) return rc;
     if (plan.exec_mode == 1) {
         // Barrier words start from zero for every fused launch.
         if ((rc = run_zero(P.flags + FLAG_BAR_COUNT, FLAG_WORDS - FLAG_BAR_COUNT, st)) != CASGD_OK)

@@ -14,6 +14,8 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTile = 64;   // Gram tile edge in sampled rows
 constexpr int kLPR = 4;     // lanes per row in the update / margin passes
+constexpr int kNT = 256;    // threads per workgroup of the dense kernels
+constexpr int kNW = kNT / 64;
 
 // One dense problem: inputs, scalars, launch geometry and workspace views.
 struct Dense {
@@ -28,13 +30,17 @@ struct Dense {
     double alpha_d, beta_d;
     int ts;                 // tiles per side = ceil(sb / kTile)
     int ntiles;             // ts (ts + 1) / 2 lower-triangular tiles
-    int ksplit;             // K splits per tile
+    int gt;                 // Gram tiles enumerated (see tile_of)
+    int bt;                 // b / kTile when b is a multiple of kTile, else 0
+    int gna;                // Gram unit height in 16-row sub-tiles: 4 (64 rows) or 2 (32 rows)
+    int ksplit;             // K splits per unit (1, 2, 4 or 8)
     int64_t kchunk;         // K elements per split (multiple of the K step)
     int nslices;            // column slices of the update / margin passes
     int64_t ldy;            // row stride (elements) of the gathered rows: n rounded up to 128
     unsigned* flags;        // FLAG_* words
     unsigned* tile_cnt;     // split-K arrival counters, one per tile
-    float* G[2];            // sb x sb, row-major, strict block-lower part used
+    float* G[2];            // sb x ldg, row-major, strict block-lower part used
+    int64_t ldg;            // row stride of G (sb plus a pad that spreads rows over channels)
     float* Gpart;           // ntiles * ksplit * 4096 split-K partial tiles
     float* rp[2];           // nslices x sb partial margins
     float* c;               // sb corrected residual weights
@@ -102,6 +108,25 @@ __device__ __forceinline__ bool tile_needed(const Dense& P, int TJ, int TI) {
     return (TI * kTile) / P.b < rlast / P.b;
 }
 
+// Enumerated Gram tile t -> tile coordinates. When b is a multiple of kTile
+// (bt = b / kTile tiles per block) only the tiles of the strict block-lower
+// triangle are enumerated: block pair q of that triangle (row-major) holds
+// tiles q*bt^2 .. (q+1)*bt^2 - 1. Otherwise every lower-triangular tile is
+// enumerated and the ones without strict block-lower entries are skipped.
+__device__ __forceinline__ bool tile_of(const Dense& P, int t, int& TJ, int& TI) {
+    if (P.bt > 0) {
+        const int bt2 = P.bt * P.bt;
+        const int q = t / bt2, r = t - q * bt2;
+        int J, I;
+        tile_coords(q, J, I);
+        TJ = (J + 1) * P.bt + r / P.bt;
+        TI = I * P.bt + r % P.bt;
+        return true;
+    }
+    tile_coords(t, TJ, TI);
+    return tile_needed(P, TJ, TI);
+}
+
 // MFMA instructions per 16-byte operand vector: FP32 4 (16x16x4), BF16/FP16 1
 // (16x16x32), FP8 2 (16x16x32 on 8 bytes each).
 template <int DT>
@@ -127,32 +152,6 @@ __device__ __forceinline__ void mfma_q(const V16& a, const V16& b, int q, v4f& a
         const long av = (long)(((uint64_t)a.w[2 * q + 1] << 32) | a.w[2 * q]);
         const long bv = (long)(((uint64_t)b.w[2 * q + 1] << 32) | b.w[2 * q]);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv, acc, 0, 0, 0);
-    }
-}
-
-// Write one 64x64 tile held as 4x4 MFMA 16x16 sub-tiles. With the 16x16
-// MFMA output layout, lane l and register v hold row 4*(l/16)+v, column l%16
-// of a sub-tile. Only strict block-lower entries inside sb x sb are stored;
-// row scales (if any) are applied here.
-__device__ __forceinline__ void store_tile(const Dense& P, float* Gout, int TJ, int TI,
-                                           const v4f (&acc)[4][4], const float (&sr)[4][4],
-                                           const float (&sc)[4]) {
-    const int lane = threadIdx.x & 63;
-    const int li = lane & 15, lg = lane >> 4;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int t = TJ * kTile + 16 * a + 4 * lg + v;
-            if (t >= P.sb) continue;
-            const int bt = t / P.b;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int u = TI * kTile + 16 * c + li;
-                if (u < P.sb && u / P.b < bt)
-                    Gout[(int64_t)t * P.sb + u] = acc[a][c][v] * sr[a][v] * sc[c];
-            }
-        }
     }
 }
 
@@ -205,45 +204,58 @@ __device__ __forceinline__ void gather_rows(const Dense& P, uint64_t h, int wave
     }
 }
 
-// One work item = one K split of one 64x64 tile, computed by one wave with
-// operands loaded from the gathered rows straight into registers (both MFMA
-// operands are K-contiguous rows of Y, so no LDS transpose is needed).
-// Lane l owns row l%16 of each 16-row sub-tile and the 16-byte K segment
-// (l/16); within a K step every (lane group, vector element) pair maps to a
-// distinct k, identically for both operands, so the products pair up. Rows
-// are zero-padded to ldy and to a multiple of kTile, so no load is guarded.
-template <int DT>
-__device__ __forceinline__ void gram_item(const Dense& P, float* Gout, uint64_t h, int item) {
+// LDS of the Gram phase: the cross-wave reduction buffer (4 waves x 4
+// sub-tiles x 64 lanes x 16 bytes) and one flag word.
+constexpr size_t kGramLds = 4 * 4 * 64 * 16 + 16;
+
+// One Gram work unit: NA*16 rows x 64 columns of the strict block-lower part
+// of G (NA = 4: a whole 64x64 tile; NA = 2: the upper or lower half of one,
+// half = 0 or 1) over K split `split`, computed by the whole workgroup.
+// The four waves split the unit's K range four ways; each computes the whole
+// unit as NA x 4 MFMA 16x16 sub-tiles with operands loaded from the gathered
+// rows straight into registers (both operands of Y Y^T are K-contiguous
+// rows, so no LDS transpose is needed; lane l owns row l%16 of a sub-tile and
+// the 16-byte K segment l/16, and any permutation of k that is the same for
+// both operands leaves the products unchanged). The waves then reduce
+// through LDS in wave order, and wave w keeps sub-tile column w. With more
+// than one split, the last workgroup to finish a unit adds the splits'
+// partials in split order. Rows are zero-padded to ldy and to a multiple of
+// kTile, so no load is guarded.
+template <int DT, int NA>
+__device__ __forceinline__ void gram_unit(const Dense& P, float* Gout, uint64_t h, int unit,
+                                          int split, unsigned char* lds) {
     using T = typename Store<DT>::T;
     constexpr int VEC = Store<DT>::kVec;
     constexpr int KSTEP = 4 * VEC;
     const int lane = threadIdx.x & 63;
-    const int tile = item / P.ksplit;
-    const int split = item - tile * P.ksplit;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile = NA == 4 ? unit : unit >> 1;
+    const int half = NA == 4 ? 0 : unit & 1;
     int TJ, TI;
-    tile_coords(tile, TJ, TI);
-    if (!tile_needed(P, TJ, TI)) return;
-    const bool diag = TJ == TI;
+    if (!tile_of(P, tile, TJ, TI)) return;   // the same for the whole workgroup
+    const int row0 = TJ * kTile + half * 32;
     const int li = lane & 15, lg = lane >> 4;
     const int slot = slot_of(h);
     const T* Y = static_cast<const T*>(pick3(P.Y, slot));
 
-    // Rows beyond sb are zero padding in the gathered buffer, so every load is
-    // unconditional.
-    const T* ra[4];
+    const T* ra[NA];
     const T* rb[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        ra[a] = Y + (int64_t)(TJ * kTile + 16 * a + li) * P.ldy + VEC * lg;
-        rb[a] = Y + (int64_t)(TI * kTile + 16 * a + li) * P.ldy + VEC * lg;
-    }
-
-    const int64_t kpad = (P.n + KSTEP - 1) / KSTEP * KSTEP;
-    const int64_t k0 = (int64_t)split * P.kchunk;
-    const int64_t k1 = min(kpad, k0 + P.kchunk);
-    v4f acc[4][4];
+    for (int a = 0; a < NA; ++a) ra[a] = Y + (int64_t)(row0 + 16 * a + li) * P.ldy + VEC * lg;
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int c = 0; c < 4; ++c) rb[c] = Y + (int64_t)(TI * kTile + 16 * c + li) * P.ldy + VEC * lg;
+
+    // K range of this wave: a quarter of the split's range, in whole K steps
+    const int64_t kpad = (P.n + KSTEP - 1) / KSTEP * KSTEP;
+    const int64_t s0 = (int64_t)split * P.kchunk;
+    const int64_t s1 = min(kpad, s0 + P.kchunk);
+    const int64_t kq = ((s1 - s0 + 3) / 4 + KSTEP - 1) / KSTEP * KSTEP;
+    const int64_t k0 = s0 + w * kq;
+    const int64_t k1 = min(s1, k0 + kq);
+
+    v4f acc[NA][4];
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[a][c] = v4f{0.f, 0.f, 0.f, 0.f};
 
@@ -254,21 +266,20 @@ __device__ __forceinline__ void gram_item(const Dense& P, float* Gout, uint64_t 
         return r;
     };
     // Ping-pong operand buffers: the loads of step k+1 are in flight while the
-    // MFMAs of step k run (no register copies, so no early wait). Diagonal
-    // tiles load B too (same addresses as A, served by the L1).
-    V16 A0[4], B0[4], A1[4], B1[4];
-    auto load = [&](V16 (&Av)[4], V16 (&Bv)[4], int64_t k) {
+    // MFMAs of step k run.
+    V16 A0[NA], B0[4], A1[NA], B1[4];
+    auto load = [&](V16 (&Av)[NA], V16 (&Bv)[4], int64_t k) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a) Av[a] = ld16(ra[a], k);
+        for (int a = 0; a < NA; ++a) Av[a] = ld16(ra[a], k);
 #pragma unroll
         for (int c = 0; c < 4; ++c) Bv[c] = ld16(rb[c], k);
     };
-    auto mma = [&](const V16 (&Av)[4], const V16 (&Bv)[4]) {
-        // q outermost: 16 independent accumulators between dependent MFMAs
+    auto mma = [&](const V16 (&Av)[NA], const V16 (&Bv)[4]) {
+        // q outermost: NA*4 independent accumulators between dependent MFMAs
 #pragma unroll
         for (int q = 0; q < mfma_per_vec<DT>(); ++q)
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < NA; ++a)
 #pragma unroll
                 for (int c = 0; c < 4; ++c) mfma_q<DT>(Av[a], Bv[c], q, acc[a][c]);
     };
@@ -284,56 +295,111 @@ __device__ __forceinline__ void gram_item(const Dense& P, float* Gout, uint64_t 
         mma(A1, B1);
     }
     if (k < k1) mma(A0, B0);
-    (void)diag;
 
-    // Row scales of the tile's rows (output layout) and columns.
-    float sr[4][4], sc[4];
-    const float* sI = pick3(P.sI, slot);
+    // Cross-wave reduction, one sub-tile row at a time: wave w sums sub-tile
+    // (a, w) over the four waves in wave order.
+    v4f* red = reinterpret_cast<v4f*>(lds);
+    v4f part[NA];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a < NA; ++a) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) red[(w * 4 + c) * 64 + lane] = acc[a][c];
+        __syncthreads();
+        part[a] = red[(0 * 4 + w) * 64 + lane] + red[(1 * 4 + w) * 64 + lane];
+        part[a] += red[(2 * 4 + w) * 64 + lane];
+        part[a] += red[(3 * 4 + w) * 64 + lane];
+        __syncthreads();
+    }
+
+    if (P.ksplit > 1) {
+        // Publish this split; the last workgroup of the unit adds all splits.
+        const int S = P.ksplit;
+        v4f* gp = reinterpret_cast<v4f*>(P.Gpart);
+        const int64_t ubase = (int64_t)unit * S;
+#pragma unroll
+        for (int a = 0; a < NA; ++a) gp[(((ubase + split) * 4 + w) * NA + a) * 64 + lane] = part[a];
+        // one release (thread 0, after the workgroup barrier) publishes the
+        // whole workgroup's partial; the last arrival acquires once
+        __syncthreads();
+        unsigned* flag = reinterpret_cast<unsigned*>(lds + kGramLds - 16);
+        if (threadIdx.x == 0) {
+            const unsigned prev = __hip_atomic_fetch_add(P.tile_cnt + unit, 1u, __ATOMIC_RELEASE,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+            if (prev == (unsigned)S - 1u) fence_acquire_agent();
+            *flag = prev;
+        }
+        __syncthreads();
+        const unsigned prev = *flag;
+        __syncthreads();
+        if (prev != (unsigned)S - 1u) return;
+        // every split's partial of this wave's sub-tiles at once, then the sum
+        // in split order
+        v4f pv[8][NA];
+#pragma unroll
+        for (int sp = 0; sp < 8; ++sp)
+#pragma unroll
+            for (int a = 0; a < NA; ++a)
+                if (sp < S)
+                    pv[sp][a] = __builtin_nontemporal_load(
+                        gp + (((ubase + sp) * 4 + w) * NA + a) * 64 + lane);
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+            part[a] = pv[0][a];
+#pragma unroll
+            for (int sp = 1; sp < 8; ++sp)
+                if (sp < S) part[a] += pv[sp][a];
+        }
+        if (threadIdx.x == 0) atomic_store_relaxed(P.tile_cnt + unit, 0u);
+    }
+
+    // Store sub-tiles (a, w): with the 16x16 MFMA output layout, lane l and
+    // register v hold row 4*(l/16)+v and column l%16 of a sub-tile. Only
+    // strict block-lower entries inside sb x sb are stored; row scales (if
+    // any) are applied here.
+    const float* sI = pick3(P.sI, slot);
+    const int u = TI * kTile + 16 * w + li;
+    const float sc = (P.scale && u < P.sb) ? sI[u] : 1.0f;
+    const int bu = u / P.b;
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int t = TJ * kTile + 16 * a + 4 * lg + v;
-            sr[a][v] = (P.scale && t < P.sb) ? sI[t] : 1.0f;
-        }
-        const int u = TI * kTile + 16 * a + li;
-        sc[a] = (P.scale && u < P.sb) ? sI[u] : 1.0f;
-    }
-
-    if (P.ksplit == 1) {
-        store_tile(P, Gout, TJ, TI, acc, sr, sc);
-        return;
-    }
-    // Split-K: publish this split, and let the last arriving split reduce all
-    // partials in split order (deterministic) and store the tile.
-    float* part = P.Gpart + ((int64_t)tile * P.ksplit + split) * 4096;
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) part[((a * 4 + c) * 4 + v) * 64 + lane] = acc[a][c][v];
-    __threadfence();
-    unsigned prev = 0;
-    if (lane == 0) prev = atomic_add_acq_rel(P.tile_cnt + tile, 1u);
-    prev = __shfl(prev, 0, kWave);
-    if (prev != (unsigned)P.ksplit - 1u) return;
-    __threadfence();
-    const float* base = P.Gpart + (int64_t)tile * P.ksplit * 4096;
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int r = ((a * 4 + c) * 4 + v) * 64 + lane;
-                float sum = 0.f;
-                for (int sp = 0; sp < P.ksplit; ++sp)
-                    sum += __builtin_nontemporal_load(base + (int64_t)sp * 4096 + r);
-                acc[a][c][v] = sum;
+            const int t = row0 + 16 * a + 4 * lg + v;
+            if (t < P.sb && u < P.sb && bu < t / P.b) {
+                const float sr = P.scale ? sI[t] : 1.0f;
+                Gout[(int64_t)t * P.ldg + u] = part[a][v] * sr * sc;
             }
-    store_tile(P, Gout, TJ, TI, acc, sr, sc);
-    if (lane == 0) atomic_store_relaxed(P.tile_cnt + tile, 0u);
+        }
+    }
+}
+
+// The Gram work of one outer iteration for the workgroups lo .. hi-1 of the
+// grid (physical indices). Work = units x K splits (units: whole tiles, or
+// half tiles when there are fewer tiles than compute units; see gna). With
+// at least ksplit workers, worker w takes only split w % ksplit: workgroups
+// are dispatched to the eight XCDs round-robin and ksplit divides 8, so each
+// XCD reads one K range of the gathered rows. `lds` holds kGramLds bytes.
+template <int DT>
+__device__ __forceinline__ void gram_phase(const Dense& P, float* Gout, uint64_t h, int lo, int hi,
+                                           unsigned char* lds) {
+    const int w = blockIdx.x;
+    const int S = P.ksplit;
+    const int U = P.gna == 4 ? P.gt : 2 * P.gt;
+    const int nw = hi - lo;
+    if (nw >= S) {
+        const int c = w % S;
+        const int first = lo + ((c - lo % S) + S) % S;
+        const int members = (hi - first + S - 1) / S;
+        for (int u = (w - first) / S; u < U; u += members) {
+            if (P.gna == 4) gram_unit<DT, 4>(P, Gout, h, u, c, lds);
+            else gram_unit<DT, 2>(P, Gout, h, u, c, lds);
+        }
+    } else {
+        for (int g = w - lo; g < U * S; g += nw) {
+            if (P.gna == 4) gram_unit<DT, 4>(P, Gout, h, g / S, g % S, lds);
+            else gram_unit<DT, 2>(P, Gout, h, g / S, g % S, lds);
+        }
+    }
 }
 
 // ------------------------------------------------------ update and margin
@@ -493,7 +559,7 @@ __device__ __forceinline__ void recurrence(const Dense& P, const float* G, const
                     for (int sl = sub; sl < P.nslices; sl += TPR) rr += (ACC)rp[(int64_t)sl * sb + t];
                     rr = group_sum_rt(rr, TPR);
                 }
-                const float* grow = G + (int64_t)t * sb;
+                const float* grow = G + (int64_t)t * P.ldg;
                 if (vec4) {
                     // kBB blocks at a time: a thread owns the 16-byte chunks sub,
                     // sub+TPR, ... of the group and issues their loads together;

@@ -23,13 +23,11 @@ int dtype_bytes(int dtype);
 int dtype_vec(int dtype);          // elements per 16-byte vector
 int slice_width_of(int dtype);     // columns per update / margin slice
 
-constexpr int kNT = 256;           // threads per workgroup of the dense kernels
-constexpr int kNW = kNT / 64;
 
 // Workspace layout of one dense problem (byte offsets, 256-byte aligned).
 struct DenseLayout {
-    int sb, ts, ntiles, needed, ksplit, nslices;
-    int64_t kchunk, ldy;
+    int sb, ts, ntiles, needed, gt, bt, gna, ksplit, nslices;
+    int64_t kchunk, ldy, ldg;
     size_t off_flags, off_tilecnt, off_G0, off_G1, off_Gpart, off_rp0, off_rp1, off_c, off_r,
         off_Y[3], off_yI[3], off_sI[3], total;
 };

@@ -40,7 +40,8 @@ __host__ __device__ inline size_t sparse_lds_bytes(int sb, int s, int acc_bytes,
     off += (size_t)kLanesPerRecWG * (s + 1) * acc_bytes;
     off = (off + 15) & ~(size_t)15;
     off += (size_t)kNW * Hp * 4;
-    return off;
+    // the head-panel Gram phase reuses the same memory
+    return off < kGramLds ? kGramLds : off;
 }
 
 // Per outer iteration h, with R recurrence workgroups (kLanesPerRecWG lanes
@@ -66,7 +67,6 @@ __global__ __launch_bounds__(kNT) void k_sparse_fit(Sparse S, uint64_t h0, int64
     const int nb = gridDim.x, wg = blockIdx.x;
     const int gw = wg * kNW + wave, ngw = nb * kNW;
     const int gtid = wg * kNT + threadIdx.x, nthr = nb * kNT;
-    const int nitems = S.gram.ntiles * S.gram.ksplit;
 
     if (threadIdx.x == 0 && wg == 0 && S.t_hist) S.t_hist[0] = (int64_t)wall_clock64();
     // Prologue: rows of h0 and h0+1; buckets and Gram of h0; margins of h0.
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(kNT) void k_sparse_fit(Sparse S, uint64_t h0, int64
     if (H > 1) sparse_gather(S, h0 + 1, gw, ngw, hrow);
     if (!grid_barrier(S.flags, nb, spin)) return;
     sparse_bucket(S, h0, gtid, nthr);
-    for (int it = gw; it < nitems; it += ngw) gram_item<DT_F32>(S.gram, spick2(S.G, (int)(h0 & 1)), h0, it);
+    gram_phase<DT_F32>(S.gram, spick2(S.G, (int)(h0 & 1)), h0, 0, nb, lds);
     if (!grid_barrier(S.flags, nb, spin)) return;
     sparse_gram_tail(S, h0, spick2(S.G, (int)(h0 & 1)), gtid, nthr);
     sparse_margins(S, h0, gw, ngw);
@@ -93,8 +93,7 @@ __global__ __launch_bounds__(kNT) void k_sparse_fit(Sparse S, uint64_t h0, int64
             const int w0 = (wg - R) * kNW + wave, nw = (nb - R) * kNW;
             const int t0 = (wg - R) * kNT + threadIdx.x, nt = (nb - R) * kNT;
             if (more) {
-                for (int it = w0; it < nitems; it += nw)
-                    gram_item<DT_F32>(S.gram, spick2(S.G, (int)((h + 1) & 1)), h + 1, it);
+                gram_phase<DT_F32>(S.gram, spick2(S.G, (int)((h + 1) & 1)), h + 1, R, nb, lds);
                 sparse_bucket(S, h + 1, t0, nt);
             }
             if (more2) sparse_gather(S, h + 2, w0, nw, hrow);
@@ -135,7 +134,7 @@ void sparse_layout(int64_t n, int b, int s, int L, int maxlen, SparseLayout* S) 
     size_t off = 0;
     auto take = [&](size_t& o, size_t bytes) { o = off; off = a256(off + bytes); };
     take(S->off_flags, FLAG_WORDS * 4);
-    take(S->off_tilecnt, (size_t)S->gl.ntiles * 4);
+    take(S->off_tilecnt, (size_t)S->gl.ntiles * 2 * 4);
     take(S->off_G0, sb * sb * 4);
     take(S->off_G1, sb * sb * 4);
     take(S->off_Gpart, S->gl.ksplit > 1 ? (size_t)S->gl.ntiles * S->gl.ksplit * 4096 * 4 : 0);
@@ -385,11 +384,15 @@ casgd_status sparse_fit(const casgd_matrix* X, const float* y, float* x_lanes,
     Gv.b = b;
     Gv.s = s;
     Gv.sb = S.sb;
+    Gv.ldg = S.sb;
     Gv.n = P.H;
     Gv.ldy = P.Hp;
     Gv.m = X->m;
     Gv.ts = SL.gl.ts;
     Gv.ntiles = SL.gl.ntiles;
+    Gv.gt = SL.gl.gt;
+    Gv.bt = SL.gl.bt;
+    Gv.gna = SL.gl.gna;
     {
         // K = H is short: split it only up to the partial buffer's capacity,
         // keeping at least 64 K elements per split
@@ -417,7 +420,7 @@ casgd_status sparse_fit(const casgd_matrix* X, const float* y, float* x_lanes,
     hipLaunchKernelGGL(k_set_lanes, dim3(1), dim3(kMaxLanes), 0, st, lp, L,
                        const_cast<double*>(S.lbeta), const_cast<float*>(S.lbs));
     CASGD_HIP(hipGetLastError());
-    if ((rc = run_zero(Gv.tile_cnt, Gv.ntiles, st)) != CASGD_OK) return rc;
+    if ((rc = run_zero(Gv.tile_cnt, 2 * Gv.ntiles, st)) != CASGD_OK) return rc;
     if ((rc = run_zero(S.flags + FLAG_BAR_COUNT, FLAG_WORDS - FLAG_BAR_COUNT, st)) != CASGD_OK)
         return rc;
 

@@ -40,7 +40,8 @@ class Model:
 class DeviceProblem:
     X32: "object"          # device FP32 m x n (kept to re-quantise after rescaling)
     y: "object"
-    Xt: "object"           # test set, FP32 MatrixRef
+    Xt32: "object"         # held-out rows, device FP32 (unpadded)
+    Xt: "object"           # the same as a padded FP32 MatrixRef
     yt: "object"
     n: int
     m: int
@@ -50,8 +51,9 @@ class DeviceProblem:
 def upload(p, dtype=cg.BF16) -> DeviceProblem:
     import torch
     X32 = torch.from_numpy(np.ascontiguousarray(p.X, dtype=np.float32)).cuda()
-    Xt = cg.dense_matrix(torch.from_numpy(np.ascontiguousarray(p.X_test, dtype=np.float32)).cuda())
-    return DeviceProblem(X32, torch.from_numpy(p.y).cuda(), Xt,
+    Xt32 = torch.from_numpy(np.ascontiguousarray(p.X_test, dtype=np.float32)).cuda()
+    vals, _ = cg.casgd_quantize(Xt32, cg.F32)
+    return DeviceProblem(X32, torch.from_numpy(p.y).cuda(), Xt32, cg.dense_matrix(vals, None, n=p.n),
                          torch.from_numpy(p.y_test).cuda(), p.n, p.m, dtype)
 
 
@@ -68,7 +70,7 @@ def stored_test(dp: DeviceProblem, q=None):
     """The held-out rows, scaled like the training rows (FP32)."""
     if q is None:
         return dp.Xt
-    vals, _ = cg.casgd_quantize_scaled(dp.Xt._keep[0], q, cg.F32)
+    vals, _ = cg.casgd_quantize_scaled(dp.Xt32, q, cg.F32)
     return cg.dense_matrix(vals, None, n=dp.n)
 
 
