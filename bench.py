@@ -190,7 +190,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--s", type=int, default=16)
     ap.add_argument("--dtype", default="f32", choices=list(DT_NAME))
-    ap.add_argument("--exec-mode", type=int, default=1)
+    ap.add_argument("--exec-mode", type=int, default=0, help="0 automatic, 1 fused, 2 stream")
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--m", type=int, default=1 << 20)
     ap.add_argument("--n", type=int, default=2048)

@@ -103,8 +103,13 @@ typedef struct {
     /* Precision of the inner residual corrections (slot u_c, Sec. 5.2):
      * 0 = automatic (FP64 when s*b >= 512, else FP32), 32 = FP32, 64 = FP64. */
     int32_t recur_prec;
-    /* 0 = automatic, 1 = one fused persistent launch for the whole fit,
-     * 2 = one launch per phase, stream ordered. */
+    /* 0 = automatic (stream ordered when s*b > 256 and b is 16, 32, 64 or
+     * 128, else fused), 1 = one fused persistent launch for the whole fit,
+     * 2 = one launch per phase, stream ordered: the recurrence then runs on
+     * one chain workgroup plus helper workgroups that add the older column
+     * blocks (b = 16, 32, 64, 128; other b use one workgroup). The two forms
+     * sum the recurrence in different orders, so they agree to rounding;
+     * each is bitwise reproducible. */
     int32_t exec_mode;
     /* Snapshots: when > 0, after every `snapshot_every` outer iterations the
      * current x is copied to x_history (device, FP32, row k = snapshot k,
@@ -113,7 +118,9 @@ typedef struct {
     int64_t snapshot_every;
     float *x_history;
     int64_t *t_history;
-    /* Grid-barrier spin limit for the fused kernel (0 = default, about 2 s). */
+    /* Spin limit of every bounded wait on the device (the fused kernel's
+     * grid barrier, the recurrence workgroups' exchange; 0 = default, about
+     * 2 s). */
     int64_t spin_limit;
     /* Tuning knobs of the fused kernel (0 = automatic):
      * fused_variant 1 = every update workgroup runs the recurrence itself

@@ -120,6 +120,8 @@ bool dense_layout(int64_t n, int dtype, int b, int s, DenseLayout* L) {
     off = align256(off + (size_t)sb * 4);
     L->off_r = off;
     off = align256(off + (size_t)sb * 4);
+    L->off_pub = off;   // recurrence exchange: 2 * sb values of up to two words
+    off = align256(off + (size_t)sb * 4 * sizeof(unsigned long long));
     const size_t sbpad = (size_t)L->ts * kTile;   // rows padded to whole Gram tiles
     for (int k = 0; k < 3; ++k) {
         L->off_Y[k] = off;
@@ -152,6 +154,8 @@ void dense_bind(const DenseLayout& L, void* ws, Dense* P) {
     P->rp[0] = reinterpret_cast<float*>(w + L.off_rp0);
     P->rp[1] = reinterpret_cast<float*>(w + L.off_rp1);
     P->c = reinterpret_cast<float*>(w + L.off_c);
+    P->r = reinterpret_cast<float*>(w + L.off_r);
+    P->pub = reinterpret_cast<unsigned long long*>(w + L.off_pub);
     P->ldy = L.ldy;
     P->ldg = L.ldg;
     for (int k = 0; k < 3; ++k) {

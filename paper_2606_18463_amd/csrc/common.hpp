@@ -166,6 +166,15 @@ __device__ __forceinline__ void atomic_store_relaxed(unsigned* p, unsigned v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Workgroup barrier that orders LDS accesses only: global loads issued
+// before it (prefetches) stay in flight across it, where __syncthreads()
+// would wait for them.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Flag words at the start of every workspace.
 enum : int {
     FLAG_NONFINITE = 0,   // set when a margin, residual or weight is NaN/Inf

@@ -14,6 +14,7 @@
 #include <cstring>
 
 #include "internal.hpp"
+#include "recurrence.hpp"
 
 namespace casgd {
 
@@ -25,8 +26,29 @@ __global__ void k_zero_u32(unsigned* p, int64_t words) {
 }
 
 template <int DT>
-__global__ __launch_bounds__(kNT) void k_gather(Dense P, uint64_t h) {
-    gather_rows<DT>(P, h, blockIdx.x * kNW + (threadIdx.x >> 6), gridDim.x * kNW);
+__global__ __launch_bounds__(kNT) void k_gather(Dense P, uint64_t h, int do_gather,
+                                                const float* rp, uint64_t hr, float* r_out) {
+    if (do_gather) gather_rows<DT>(P, h, blockIdx.x * kNW + (threadIdx.x >> 6), gridDim.x * kNW);
+    if (rp) {
+        // margins of outer iteration hr: eight lanes per row, lane e adding
+        // the slices e, e+8, ... in order, then a fixed tree over the eight
+        // lanes; times the row scale
+        const float* sI = pick3(P.sI, slot_of(hr));
+        const int e = threadIdx.x & 7;
+        const int rows_per_pass = gridDim.x * (blockDim.x >> 3);
+        for (int t0 = blockIdx.x * (blockDim.x >> 3); t0 < P.sb; t0 += rows_per_pass) {
+            const int t = t0 + (threadIdx.x >> 3);
+            float a = 0.f;
+            if (t < P.sb) {
+#pragma unroll 8
+                for (int sl = e; sl < P.nslices; sl += 8) a += rp[(int64_t)sl * P.sb + t];
+            }
+            a += shfl_xor(a, 1);
+            a += shfl_xor(a, 2);
+            a += shfl_xor(a, 4);
+            if (t < P.sb && e == 0) r_out[t] = a * sI[t];
+        }
+    }
 }
 
 template <int DT>
@@ -182,7 +204,17 @@ namespace {
 template <int DT>
 casgd_status launch_gather_t(const Dense& P, uint64_t h, hipStream_t st) {
     const int grid = std::max(1, std::min((P.sb + kNW - 1) / kNW, 4 * device_cus()));
-    hipLaunchKernelGGL(k_gather<DT>, dim3(grid), dim3(kNT), 0, st, P, h);
+    hipLaunchKernelGGL(k_gather<DT>, dim3(grid), dim3(kNT), 0, st, P, h, 1, nullptr, 0,
+                       nullptr);
+    CASGD_HIP(hipGetLastError());
+    return CASGD_OK;
+}
+
+template <int DT>
+casgd_status launch_gather_reduce_t(const Dense& P, uint64_t h, int do_gather, const float* rp,
+                                    uint64_t hr, float* r_out, hipStream_t st) {
+    const int grid = std::max(1, std::min((P.sb + kNW - 1) / kNW, 4 * device_cus()));
+    hipLaunchKernelGGL(k_gather<DT>, dim3(grid), dim3(kNT), 0, st, P, h, do_gather, rp, hr, r_out);
     CASGD_HIP(hipGetLastError());
     return CASGD_OK;
 }
@@ -204,6 +236,14 @@ casgd_status launch_update_t(const Dense& P, const float* c, uint64_t h, int do_
                        do_margin, rp_out, snap_row);
     CASGD_HIP(hipGetLastError());
     return CASGD_OK;
+}
+
+template <typename ACC, int NV>
+__global__ __launch_bounds__(kNT) void k_rec_multi(Dense P, const float* G, const float* r,
+                                                   const float* y, float* c, float* delta_out,
+                                                   unsigned long long spin) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    recurrence_multi<ACC, NV>(P, G, r, y, c, delta_out, P.pub, spin, lds);
 }
 
 template <typename ACC>
@@ -306,6 +346,55 @@ casgd_status run_gather(const Dense& P, int dtype, uint64_t h, hipStream_t st) {
     }
 }
 
+static casgd_status run_gather_reduce(const Dense& P, int dtype, uint64_t h, int do_gather,
+                                      const float* rp, uint64_t hr, float* r_out, hipStream_t st) {
+    switch (dtype) {
+        case DT_F32: return launch_gather_reduce_t<DT_F32>(P, h, do_gather, rp, hr, r_out, st);
+        case DT_BF16: return launch_gather_reduce_t<DT_BF16>(P, h, do_gather, rp, hr, r_out, st);
+        case DT_F16: return launch_gather_reduce_t<DT_F16>(P, h, do_gather, rp, hr, r_out, st);
+        default: return launch_gather_reduce_t<DT_FP8>(P, h, do_gather, rp, hr, r_out, st);
+    }
+}
+
+// The multi-workgroup recurrence handles b = 16, 32, 64, 128.
+static bool rec_multi_ok(const Dense& P) {
+    return P.b == 16 || P.b == 32 || P.b == 64 || P.b == 128;
+}
+
+template <typename ACC, int NV>
+static casgd_status launch_rec_multi_t(const Dense& P, const float* G, const float* r,
+                                       const float* y, float* c, float* delta_out,
+                                       unsigned long long spin, hipStream_t st) {
+    constexpr int W = rec_window<NV>();
+    const int R = P.s - W - 1 > 0 ? P.s - W - 1 : 0;
+    const size_t lds = (size_t)(P.sb + P.s + 1) * sizeof(ACC);
+    Dense Pc = P;
+    void* args[] = {&Pc, const_cast<float**>(&G), const_cast<float**>(&r), const_cast<float**>(&y),
+                    &c, &delta_out, &spin};
+    CASGD_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_rec_multi<ACC, NV>),
+                                         dim3(1 + R), dim3(kNT), args, (unsigned)lds, st));
+    return CASGD_OK;
+}
+
+template <typename ACC>
+static casgd_status launch_rec_multi_acc(const Dense& P, const float* G, const float* r,
+                                         const float* y, float* c, float* delta_out,
+                                         unsigned long long spin, hipStream_t st) {
+    switch (P.b) {
+        case 16: return launch_rec_multi_t<ACC, 1>(P, G, r, y, c, delta_out, spin, st);
+        case 32: return launch_rec_multi_t<ACC, 2>(P, G, r, y, c, delta_out, spin, st);
+        case 64: return launch_rec_multi_t<ACC, 4>(P, G, r, y, c, delta_out, spin, st);
+        default: return launch_rec_multi_t<ACC, 8>(P, G, r, y, c, delta_out, spin, st);
+    }
+}
+
+static casgd_status run_rec_multi(const Dense& P, const float* G, const float* r, const float* y,
+                                  float* c, float* delta_out, bool fp64, unsigned long long spin,
+                                  hipStream_t st) {
+    return fp64 ? launch_rec_multi_acc<double>(P, G, r, y, c, delta_out, spin, st)
+                : launch_rec_multi_acc<float>(P, G, r, y, c, delta_out, spin, st);
+}
+
 casgd_status run_gram(const Dense& P, int dtype, float* Gout, uint64_t h, hipStream_t st) {
     switch (dtype) {
         case DT_F32: return launch_gram_t<DT_F32>(P, Gout, h, st);
@@ -375,7 +464,8 @@ casgd_status plan_fit(const Dense& P, int dtype, const casgd_opts* o, int64_t H,
         return CASGD_EINVAL;
     }
     plan->recur64 = prec == 64 || (prec == 0 && sb >= 512);
-    plan->exec_mode = (o && o->exec_mode) ? o->exec_mode : 1;
+    plan->exec_mode = (o && o->exec_mode) ? o->exec_mode
+                                           : (sb > 256 && rec_multi_ok(P) ? 2 : 1);
     if (plan->exec_mode != 1 && plan->exec_mode != 2) {
         set_error("exec_mode must be 0, 1 or 2 (got %d)", plan->exec_mode);
         return CASGD_EINVAL;
@@ -401,7 +491,7 @@ casgd_status plan_fit(const Dense& P, int dtype, const casgd_opts* o, int64_t H,
         plan->exec_mode = 2;
         return CASGD_OK;
     }
-    const int units = P.s > 1 ? (P.gt + kNW - 1) / kNW * P.ksplit : 0;
+    const int units = P.s > 1 ? (P.gna == 4 ? P.gt : 2 * P.gt) * P.ksplit : 0;
     int want = std::max(P.nslices, units + (variant == 2 ? 1 : 0));
     want = std::max(want, variant == 2 ? 2 : 1);
     if (o && o->grid_blocks > 0) want = o->grid_blocks;
@@ -437,9 +527,15 @@ casgd_status run_fit(const Dense& P, int dtype, uint64_t h0, int64_t H, const Fi
         }
     }
     // Stream-ordered: gather(h0), margin(h0); then per outer: gram(h),
-    // gather(h+1), recurrence(h), update(h) fused with margin(h+1).
+    // gather(h+1) (with the reduction of the margins of h when the
+    // multi-workgroup recurrence runs), recurrence(h), update(h) fused with
+    // margin(h+1).
+    const bool multi = rec_multi_ok(P);
     if ((rc = run_gather(P, dtype, h0, st)) != CASGD_OK) return rc;
     if ((rc = run_update_margin(P, dtype, nullptr, 0, 0, h0, 1, P.rp[0], -1, st)) != CASGD_OK)
+        return rc;
+    // the recurrence's exchange words start from zero (each launch clears them)
+    if (multi && (rc = run_zero(reinterpret_cast<unsigned*>(P.pub), (int64_t)P.sb * 8, st)) != CASGD_OK)
         return rc;
     for (int64_t hh = 0; hh < H; ++hh) {
         const uint64_t h = h0 + (uint64_t)hh;
@@ -447,10 +543,19 @@ casgd_status run_fit(const Dense& P, int dtype, uint64_t h0, int64_t H, const Fi
         const bool snap = P.snap_every > 0 && ((hh + 1) % P.snap_every) == 0;
         const int64_t snap_row = snap ? (hh + 1) / P.snap_every - 1 : -1;
         if ((rc = run_gram(P, dtype, P.G[0], h, st)) != CASGD_OK) return rc;
-        if (more && (rc = run_gather(P, dtype, h + 1, st)) != CASGD_OK) return rc;
-        if ((rc = run_recurrence(P, P.G[0], P.rp[0], h, nullptr, nullptr, P.c, nullptr,
-                                 plan.recur64 != 0, st)) != CASGD_OK)
-            return rc;
+        if (multi) {
+            if ((rc = run_gather_reduce(P, dtype, h + 1, more ? 1 : 0, P.rp[0], h, P.r, st)) !=
+                CASGD_OK)
+                return rc;
+            if ((rc = run_rec_multi(P, P.G[0], P.r, P.yI[slot_of_host(h)], P.c, nullptr,
+                                    plan.recur64 != 0, plan.spin, st)) != CASGD_OK)
+                return rc;
+        } else {
+            if (more && (rc = run_gather(P, dtype, h + 1, st)) != CASGD_OK) return rc;
+            if ((rc = run_recurrence(P, P.G[0], P.rp[0], h, nullptr, nullptr, P.c, nullptr,
+                                     plan.recur64 != 0, st)) != CASGD_OK)
+                return rc;
+        }
         if ((rc = run_update_margin(P, dtype, P.c, h, 1, h + 1, more ? 1 : 0, P.rp[0], snap_row,
                                     st)) != CASGD_OK)
             return rc;

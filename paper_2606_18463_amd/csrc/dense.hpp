@@ -44,6 +44,8 @@ struct Dense {
     float* Gpart;           // ntiles * ksplit * 4096 split-K partial tiles
     float* rp[2];           // nslices x sb partial margins
     float* c;               // sb corrected residual weights
+    float* r;               // sb reduced margins (row scales applied)
+    unsigned long long* pub; // tagged words exchanged by the recurrence workgroups
     void* Y[3];             // gathered rows of outer iteration h in slot h % 3 (sb x ldy)
     float* yI[3];           // their labels
     float* sI[3];           // their row scales (1 when X has none)
@@ -60,6 +62,7 @@ struct Dense {
 };
 
 __device__ __forceinline__ int slot_of(uint64_t h) { return (int)(h % 3ull); }
+inline int slot_of_host(uint64_t h) { return (int)(h % 3ull); }
 
 // Buffer selection by explicit selects: indexing the by-value kernel argument
 // with a run-time index would force the whole struct into scratch memory.

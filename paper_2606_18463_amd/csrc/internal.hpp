@@ -28,7 +28,7 @@ int slice_width_of(int dtype);     // columns per update / margin slice
 struct DenseLayout {
     int sb, ts, ntiles, needed, gt, bt, gna, ksplit, nslices;
     int64_t kchunk, ldy, ldg;
-    size_t off_flags, off_tilecnt, off_G0, off_G1, off_Gpart, off_rp0, off_rp1, off_c, off_r,
+    size_t off_flags, off_tilecnt, off_G0, off_G1, off_Gpart, off_rp0, off_rp1, off_c, off_r, off_pub,
         off_Y[3], off_yI[3], off_sI[3], total;
 };
 

@@ -53,7 +53,7 @@ def test_batch_equals_solo_and_oracle(cg, fmt):
         cg.casgd_check(ws)
     for i, q in enumerate(probs):
         solo = torch.zeros(q["p"].n, device="cuda")
-        o = cg.opts(fused_variant=batch[i]["variant"])
+        o = cg.opts(exec_mode=1, fused_variant=batch[i]["variant"])
         cg.casgd_fit(q["X"], q["y"], solo, q["eta"], q["lam"], q["b"], q["s"], q["seed"], 0,
                      q["H"], opts=o)
         assert torch.equal(solo, xs[i]), i
@@ -73,7 +73,7 @@ def test_batch_explicit_groups(cg):
         cg.casgd_check(ws)
     for i, q in enumerate(probs):
         solo = torch.zeros(q["p"].n, device="cuda")
-        o = cg.opts(fused_variant=batch[i]["variant"])
+        o = cg.opts(exec_mode=1, fused_variant=batch[i]["variant"])
         cg.casgd_fit(q["X"], q["y"], solo, q["eta"], q["lam"], q["b"], q["s"], q["seed"], 0,
                      q["H"], opts=o)
         assert torch.equal(solo, xs[i]), i

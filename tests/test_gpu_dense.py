@@ -199,14 +199,37 @@ def test_c1_fit_matches_oracle(cg, c1data, mode, variant):
     assert abs(lg - lo) / lo < 1e-5
 
 
+@pytest.mark.parametrize("b,s,prec", [(16, 16, 32), (16, 24, 64), (32, 12, 32), (64, 8, 64),
+                                      (64, 16, 64), (128, 4, 32), (128, 6, 64), (64, 32, 0)])
+def test_stream_ordered_multi_workgroup_recurrence(cg, b, s, prec):
+    """The stream-ordered fit runs the recurrence on one chain workgroup plus
+    helper workgroups (s > W + 1); its trajectory matches the FP64 oracle and
+    the fused launch (single-workgroup recurrence) to rounding."""
+    p = dense_logreg(3000, 136, 5, var=1 / 136, noise_var=0.1, dtype=np.float32)
+    X = cg.dense_matrix(_to_dev(p.X))
+    y = _to_dev(p.y)
+    H = max(3, 256 // s)
+    xg = _fit(cg, X, y, np.zeros(136, np.float32), 0.5, 1e-4, b, s, 9, H, exec_mode=2,
+              recur_prec=prec)
+    xf = _fit(cg, X, y, np.zeros(136, np.float32), 0.5, 1e-4, b, s, 9, H, exec_mode=1,
+              recur_prec=prec)
+    xo = R.casgd(p.X, p.y, np.zeros(136), 0.5, 1e-4, b, s, 9, 0, H)
+    assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) < 1e-4
+    assert np.linalg.norm(xg - xf) / np.linalg.norm(xo) < 1e-4
+
+
 def test_exec_modes_bitwise_equal(cg, c1data):
+    """The fused variants share every device function: bitwise equal. The
+    stream-ordered form sums the recurrence in another order (near and far
+    parts): bitwise reproducible, equal to the fused result to rounding."""
     X32 = c1data.X.astype(np.float32)
     Xs = cg.dense_matrix(_to_dev(X32))
     y = _to_dev(c1data.y)
     runs = [_fit(cg, Xs, y, np.zeros(256, np.float32), 0.5, 1e-4, 16, 4, 42, 50,
-                 exec_mode=m, fused_variant=v) for m, v in [(1, 1), (1, 2), (2, 0), (1, 1)]]
-    for r in runs[1:]:
-        assert np.array_equal(r, runs[0])
+                 exec_mode=m, fused_variant=v) for m, v in [(1, 1), (1, 2), (1, 1), (2, 0), (2, 0)]]
+    assert np.array_equal(runs[1], runs[0]) and np.array_equal(runs[2], runs[0])
+    assert np.array_equal(runs[4], runs[3])
+    assert np.linalg.norm(runs[3] - runs[0]) / np.linalg.norm(runs[0]) < 1e-5
 
 
 def test_gpu_s_step_equals_gpu_sgd(cg, c1data):
@@ -257,7 +280,7 @@ def test_snapshots(cg, c1data, mode):
     cg.casgd_fit(Xs, y, x, 0.5, 1e-4, 16, 4, 42, 0, 20, opts=o)
     ref = _to_dev(np.zeros(256, np.float32))
     for k in range(4):
-        cg.casgd_fit(Xs, y, ref, 0.5, 1e-4, 16, 4, 42, 5 * k, 5)
+        cg.casgd_fit(Xs, y, ref, 0.5, 1e-4, 16, 4, 42, 5 * k, 5, opts=cg.opts(exec_mode=mode))
         assert torch.equal(hist[k], ref)
     if mode == 1:
         t = th.cpu().numpy()
