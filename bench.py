@@ -183,6 +183,89 @@ def eta_sweep(cg, wl: Workload, etas):
     return out
 
 
+TARGET_GAP = 1e-3   # time-to-target: first snapshot with test loss <= L* (1 + gap)
+
+
+def golden_target():
+    """L*: the FP64 oracle's plain SGD test loss after the full 20-epoch budget
+    (tests/golden/c2_target.json, written by tests/golden/make_c2_target.py)."""
+    with open(os.path.join(ROOT, "tests", "golden", "c2_target.json")) as f:
+        return json.load(f)
+
+
+def time_to_target(cg, wl: Workload, Xt, yt, dtype: str, s: int, epochs: float, snaps_per_epoch: int,
+                   L_star: float):
+    """Fit from zero for `epochs` epochs in one fused launch with snapshots of x
+    (and the device clock) every 1/snaps_per_epoch epoch; the test losses of
+    the snapshots are computed afterwards, outside the timed launch."""
+    import torch
+    X, y, keep = upload(cg, wl, dtype)
+    b = B_C2
+    steps_per_epoch = wl.m // b
+    every = max(1, steps_per_epoch // (snaps_per_epoch * s))      # outer iterations
+    H = int(epochs * steps_per_epoch / s) // every * every
+    k = H // every
+    hist = torch.zeros(k, wl.n, device="cuda")
+    th = torch.zeros(k + 1, dtype=torch.int64, device="cuda")
+    x = torch.zeros(wl.n, device="cuda")
+    o = cg.opts(exec_mode=1, snapshot_every=every, x_history=hist, t_history=th)
+    ws = cg.casgd_fit(X, y, x, ETA_C2, LAMBDA_C2, b, s, SEED, 0, H, opts=o)
+    torch.cuda.synchronize()
+    cg.casgd_check(ws)
+    losses = cg.casgd_logloss(Xt, yt, hist).cpu().numpy()
+    t = (th.cpu().numpy() - int(th[0])) * 1e-8           # device clock: 100 MHz
+    target = L_star * (1.0 + TARGET_GAP)
+    hit = np.nonzero(losses <= target)[0]
+    first = int(hit[0]) if hit.size else None
+    del X, keep
+    return {"storage": dtype, "s": s, "b": b, "updates_per_snapshot": every * s,
+            "updates_to_target": None if first is None else (first + 1) * every * s,
+            "seconds_to_target": None if first is None else round(float(t[first + 1]), 6),
+            "seconds_total": round(float(t[-1]), 6), "updates_total": H * s,
+            "loss_at_target": None if first is None else round(float(losses[first]), 7),
+            "final_loss": round(float(losses[-1]), 7),
+            "updates_per_s": round(H * s / float(t[-1]), 1)}
+
+
+def copy_calibration(nbytes: int = 1 << 30, reps: int = 3):
+    """A plain device copy of known size: the reference for scaling the
+    FETCH_SIZE / WRITE_SIZE counters (run under rocprofv3 --pmc)."""
+    import torch
+    a = torch.empty(nbytes // 4, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps}))
+
+
+def sources_hash() -> str:
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2606_18463_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp"))
+                    + glob.glob(os.path.join(csrc, "*.cpp"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name: str, outer_per_launch: int):
+    """HBM bytes per launch from a committed PMC summary (profiles/<name>.json),
+    or None when it is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", name + ".json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_hash") != sources_hash():
+        return None
+    return round(d["hbm_bytes_per_outer"] * outer_per_launch)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,7 +281,15 @@ def main():
     ap.add_argument("--eta-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-gram", action="store_true")
+    ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-target runs")
+    ap.add_argument("--ttt-epochs", type=float, default=4.0)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--source-hash", action="store_true")
     args = ap.parse_args()
+    if args.source_hash:
+        print(sources_hash())
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -210,18 +301,23 @@ def main():
     import paper_2606_18463_amd as cg
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     cg._lib.load()
+    if args.copy_calib:
+        copy_calibration()
+        return
 
     s, b, n, dtype = args.s, B_C2, args.n, args.dtype
-    wl = Workload(args.m, n, with_test=args.eta_sweep)
+    wl = Workload(args.m, n, with_test=args.eta_sweep or not args.no_ttt)
     if args.eta_sweep:
         res = eta_sweep(cg, wl, [2.0 ** k for k in range(-2, 7)])
         print(json.dumps({"eta_sweep": res}))
         return
 
     X, y, _keep = upload(cg, wl, dtype)
-    # default K: about 2^16 SGD updates (a few hundred ms), W: 5% of it
+    # default K: 2^16 SGD updates (a few hundred ms); the warm-up launch has
+    # the same length, so every launch of the kernel in a profile of this
+    # command has the timed launch's duration
     K = args.steps if args.steps is not None else max(8, (1 << 16) // s)
-    W = args.warmup if args.warmup is not None else max(2, K // 20)
+    W = args.warmup if args.warmup is not None else K
     okw = dict(exec_mode=args.exec_mode, fused_variant=args.variant)
     ms, x, ws = timed_fit(cg, X, y, n, b, s, ETA_C2, LAMBDA_C2, K, W, okw)
     ups = s * K / (ms * 1e-3)
@@ -232,17 +328,21 @@ def main():
     peak_f = PEAK[f"{dtype}_TFLOPs"]
     ach_f = fl / (ms * 1e-3) / 1e12
     ach_b = by / (ms * 1e-3) / 1e9
+    tname = f"traffic_k_fit_dense_{args.m}x{n}_{dtype}_s{s}"
+    traffic = measured_traffic(tname, K)
     if s > 1:
         roof = {"kernel": "k_fit (fused launch, all steps)", "bound": "mfma",
                 "achieved": round(ach_f, 3), "peak": peak_f, "unit": "TFLOP/s",
-                "frac": round(ach_f / peak_f, 4), "traffic": None}
+                "frac": round(ach_f / peak_f, 4), "traffic": traffic,
+                "flops_per_launch": fl, "algorithmic_bytes_per_launch": by}
     else:
         roof = {"kernel": "k_fit (fused launch, all steps)", "bound": "hbm",
                 "achieved": round(ach_b, 2), "peak": PEAK["hbm_GBps"], "unit": "GB/s",
-                "frac": round(ach_b / PEAK["hbm_GBps"], 5), "traffic": None}
+                "frac": round(ach_b / PEAK["hbm_GBps"], 5), "traffic": traffic,
+                "algorithmic_bytes_per_launch": by}
 
     out = {
-        "metric": "SGD updates/s (s-step CA-SGD, dense FP32 workload)",
+        "metric": "SGD updates/s & time-to-1e-3 loss gap: CA-SGD mixed vs plain, % roofline",
         "value": round(ups, 1), "unit": "SGD updates/s", "n_gpus": 1, "steps": K,
         "warmup": W, "ms_per_step": round(ms / K, 6), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
@@ -258,15 +358,41 @@ def main():
     if args.sweep:
         rows = []
         for ss in (1, 4, 16, 32):
-            for em in (1, 2):
+            for em, var in ((1, 0), (1, 2), (2, 0)):
+                if ss == 1 and var == 2:
+                    continue
                 Ks = max(8, (1 << 15) // ss)
                 mss, _, _ = timed_fit(cg, X, y, n, b, ss, ETA_C2, LAMBDA_C2, Ks, max(2, Ks // 20),
-                                      dict(exec_mode=em))
-                rows.append({"s": ss, "exec_mode": em,
+                                      dict(exec_mode=em, fused_variant=var))
+                rows.append({"s": ss, "exec_mode": em, "variant": var,
                              "updates_per_s": round(ss * Ks / (mss * 1e-3), 1),
                              "us_per_outer": round(mss * 1e3 / Ks, 3)})
                 log(f"[sweep] {rows[-1]}")
         out["sweep"] = rows
+    if not args.no_ttt:
+        del X, y, _keep, x, ws
+        torch.cuda.empty_cache()
+        g = golden_target()
+        Xt, _ = cg.casgd_quantize(torch.from_numpy(wl.p.X_test).cuda(), cg.F32)
+        Xt = cg.dense_matrix(Xt, None, n=n)
+        yt = torch.from_numpy(wl.p.y_test).cuda()
+        runs = []
+        for name, dt, ss in (("plain SGD, FP32", "f32", 1), ("CA-SGD, FP32", "f32", 16),
+                             ("CA-SGD mixed, BF16 X", "bf16", 16),
+                             ("CA-SGD mixed, FP8-e4m3 X", "fp8", 16)):
+            r = time_to_target(cg, wl, Xt, yt, dt, ss, args.ttt_epochs, 16, g["L_star"])
+            r["name"] = name
+            runs.append(r)
+            log(f"[ttt] {name}: {r}")
+        plain = runs[0]["seconds_to_target"]
+        ttt = {"L_star": g["L_star"], "gap": TARGET_GAP,
+               "target": g["L_star"] * (1 + TARGET_GAP),
+               "L_star_source": "FP64 oracle plain SGD, 20 epochs (tests/golden/c2_target.json)",
+               "runs": runs}
+        for r in runs[1:]:
+            if plain and r["seconds_to_target"]:
+                r["speedup_vs_plain"] = round(plain / r["seconds_to_target"], 2)
+        out["time_to_target"] = ttt
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, b, s, ETA_C2, LAMBDA_C2)
     print(json.dumps(out), flush=True)

@@ -103,13 +103,12 @@ typedef struct {
     /* Precision of the inner residual corrections (slot u_c, Sec. 5.2):
      * 0 = automatic (FP64 when s*b >= 512, else FP32), 32 = FP32, 64 = FP64. */
     int32_t recur_prec;
-    /* 0 = automatic (stream ordered when s*b > 256 and b is 16, 32, 64 or
-     * 128, else fused), 1 = one fused persistent launch for the whole fit,
-     * 2 = one launch per phase, stream ordered: the recurrence then runs on
-     * one chain workgroup plus helper workgroups that add the older column
-     * blocks (b = 16, 32, 64, 128; other b use one workgroup). The two forms
-     * sum the recurrence in different orders, so they agree to rounding;
-     * each is bitwise reproducible. */
+    /* 0 = automatic (fused), 1 = one fused persistent launch for the whole
+     * fit, 2 = one launch per phase, stream ordered. With s*b > 256 and b =
+     * 16, 32, 64 or 128 both run the recurrence on one chain workgroup plus
+     * helper workgroups that add the older column blocks (fused variant 3);
+     * otherwise on one workgroup. Forms that sum the recurrence in different
+     * orders agree to rounding; each is bitwise reproducible. */
     int32_t exec_mode;
     /* Snapshots: when > 0, after every `snapshot_every` outer iterations the
      * current x is copied to x_history (device, FP32, row k = snapshot k,
@@ -127,6 +126,9 @@ typedef struct {
      *   (one grid barrier per outer iteration; for small s*b),
      * fused_variant 2 = one workgroup runs the recurrence while the others
      *   compute the next outer iteration's Gram (two barriers);
+     * fused_variant 3 = the multi-workgroup recurrence (chain + helpers, as
+     *   in exec_mode 2) runs while the other workgroups compute the next
+     *   Gram; three barriers (b = 16, 32, 64, 128; not in casgd_fit_batch);
      * grid_blocks = number of workgroups of the fused launch (capped at the
      *   number that can be resident). */
     int32_t fused_variant;

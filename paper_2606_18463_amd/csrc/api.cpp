@@ -495,6 +495,14 @@ casgd_status casgd_fit_batch(const casgd_problem* probs, int32_t count, int64_t 
         }
         FitPlan plan;
         if ((rc = plan_fit(D[i], dtype, &o, q.n_outer, &plan)) != CASGD_OK) return rc;
+        if (plan.variant == 3) {
+            // the batched launch runs the single-workgroup recurrence
+            if (q.variant == 3) {
+                set_error("problem %d: fused_variant 3 is not available in a batched launch", i);
+                return CASGD_EUNSUPPORTED;
+            }
+            plan.variant = 2;
+        }
         D[i].h0 = q.outer_begin;
         D[i].H = q.n_outer;
         D[i].variant = plan.variant;

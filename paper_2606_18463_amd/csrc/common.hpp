@@ -179,9 +179,13 @@ __device__ __forceinline__ void lds_barrier() {
 enum : int {
     FLAG_NONFINITE = 0,   // set when a margin, residual or weight is NaN/Inf
     FLAG_TIMEOUT = 1,     // set when a grid barrier exceeded its spin limit
-    FLAG_BAR_COUNT = 16,  // grid barrier arrival counter (own 64-byte line)
-    FLAG_BAR_GEN = 32,    // grid barrier generation (own 64-byte line)
-    FLAG_WORDS = 64
+    FLAG_BAR_COUNT = 32,  // grid barrier: generation word, then the top arrival
+                          // counter, then eight group counters, each on its
+                          // own 128-byte line (words 32 .. 351)
+    FLAG_BAR_GEN = 32,
+    FLAG_BAR_TOP = 64,
+    FLAG_BAR_GROUP = 96,  // + 32 * group
+    FLAG_WORDS = 352
 };
 
 // Entry points without a workspace pass flags == nullptr and report nothing.
@@ -191,6 +195,10 @@ __device__ __forceinline__ void raise_flag(unsigned* flags, int which) {
 
 // Grid-wide barrier for a launch whose workgroups are all resident (the
 // cooperative launch guarantees it). Sense is kept in a generation counter.
+// Arrival is hierarchical: member m counts in group m % 8 (one counter per
+// group, each on its own cache line), and the last arrival of each group
+// counts at the top; the last one there advances the generation. That keeps
+// the number of atomics serialised on one address near nblocks / 8 + 8.
 // One thread per workgroup synchronises for the whole workgroup (after a
 // workgroup barrier, its agent-scope release and acquire cover every wave):
 // agent-scope release and acquire write back and invalidate the XCD's L2, so
@@ -199,24 +207,35 @@ __device__ __forceinline__ void raise_flag(unsigned* flags, int which) {
 // The wait is bounded: after `spin_limit` polls the timeout flag is raised
 // and every workgroup leaves the barrier (and then the kernel) at once, so a
 // launch can never wait forever. Returns false when the kernel must stop.
-__device__ __forceinline__ bool grid_barrier(unsigned* flags, unsigned nblocks,
+__device__ __forceinline__ bool grid_barrier(unsigned* flags, unsigned member, unsigned nblocks,
                                              unsigned long long spin_limit) {
     __shared__ int s_stop;
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned* count = flags + FLAG_BAR_COUNT;
+        const unsigned ng = nblocks < 8u ? nblocks : 8u;
+        const unsigned g = member % ng;
+        const unsigned in_group = (nblocks - g + ng - 1) / ng;
         unsigned* gen = flags + FLAG_BAR_GEN;
-        const unsigned g = atomic_load_relaxed(gen);
-        const unsigned arrived =
-            __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned* top = flags + FLAG_BAR_TOP;
+        unsigned* cnt = flags + FLAG_BAR_GROUP + 32 * g;
+        const unsigned g0 = atomic_load_relaxed(gen);
         int stop = 0;
-        if (arrived == nblocks - 1) {
+        bool advanced = false;
+        const unsigned a = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (a == in_group - 1) {
             fence_acquire_agent();
-            atomic_store_relaxed(count, 0u);
-            atomic_store_release(gen, g + 1u);
-        } else {
+            atomic_store_relaxed(cnt, 0u);
+            const unsigned t =
+                __hip_atomic_fetch_add(top, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (t == ng - 1) {
+                atomic_store_relaxed(top, 0u);
+                atomic_store_release(gen, g0 + 1u);
+                advanced = true;
+            }
+        }
+        if (!advanced) {
             unsigned long long spins = 0;
-            while (atomic_load_relaxed(gen) == g) {
+            while (atomic_load_relaxed(gen) == g0) {
                 if (++spins > spin_limit) {
                     raise_flag(flags, FLAG_TIMEOUT);
                     stop = 1;

@@ -15,6 +15,7 @@
 
 #include "internal.hpp"
 #include "recurrence.hpp"
+#include "fit.hpp"
 
 namespace casgd {
 
@@ -88,99 +89,6 @@ __global__ __launch_bounds__(kNT) void k_recurrence(Dense P, const float* G, con
     recurrence<ACC, kNT>(P, G, rp, h, r_in, y_in, c, delta_out, dl, pw, tpr);
 }
 
-// LDS bytes of the persistent kernel: recurrence history, decay powers, the
-// workgroup's copy of c (variant 1), and the update's reduction buffers.
-__host__ __device__ inline size_t fit_lds_bytes(int sb, int s, int acc_bytes, int kw) {
-    size_t off = (size_t)sb * acc_bytes;
-    off += (size_t)(s + 1) * acc_bytes;
-    off = (off + 15) & ~(size_t)15;
-    off += (size_t)sb * 4;                // c copy
-    off += (size_t)kNW * kw * 4 + kw * 4; // red + xs
-    // the Gram phase reuses the same memory (phases never overlap in a workgroup)
-    return s > 1 && off < kGramLds ? kGramLds : off;
-}
-
-// One problem's whole fit on the workgroups wg = 0 .. nb-1 of its group (the
-// grid, or one group of a batched launch), with the group's own barrier.
-template <int DT, typename ACC>
-__device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigned long long spin,
-                                         unsigned char* lds) {
-    constexpr int KW = slice_width<DT>();
-    ACC* dl = reinterpret_cast<ACC*>(lds);
-    ACC* pw = dl + P.sb;
-    size_t off = (size_t)P.sb * sizeof(ACC) + (size_t)(P.s + 1) * sizeof(ACC);
-    off = (off + 15) & ~(size_t)15;
-    float* cl = reinterpret_cast<float*>(lds + off);
-    float* red = cl + P.sb;
-    float* xs = red + kNW * KW;
-
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const bool has_gram = P.s > 1;
-    // physical workgroup range of this problem (the Gram phase maps K splits
-    // to XCDs by physical index)
-    const int base = (int)blockIdx.x - wg;
-    const uint64_t h0 = P.h0;
-    const int64_t H = P.H;
-    const int tpr = P.tpr;
-
-    if (threadIdx.x == 0 && wg == 0 && P.t_hist) P.t_hist[0] = (int64_t)wall_clock64();
-    const int gw = wg * kNW + wave, ngw = nb * kNW;
-
-    // Prologue: gather the rows of h0 and h0+1; then the Gram of h0 and the
-    // margins of h0 from the incoming x.
-    gather_rows<DT>(P, h0, gw, ngw);
-    if (H > 1) gather_rows<DT>(P, h0 + 1, gw, ngw);
-    if (!grid_barrier(P.flags, nb, spin)) return;
-    if (has_gram) gram_phase<DT>(P, P.G[0], h0, base, base + nb, lds);
-    for (int sl = wg; sl < P.nslices; sl += nb)
-        update_margin_slice<DT, kNW>(P, sl, nullptr, 0, false, h0, true, P.rp[0], red, xs, -1);
-    if (!grid_barrier(P.flags, nb, spin)) return;
-
-    for (int64_t hh = 0; hh < H; ++hh) {
-        const uint64_t h = h0 + (uint64_t)hh;
-        const int cur = (int)(hh & 1), nxt = cur ^ 1;
-        const bool more = hh + 1 < H;
-        const bool more2 = hh + 2 < H;
-        const bool snap = P.snap_every > 0 && ((hh + 1) % P.snap_every) == 0;
-        const int64_t snap_row = snap ? (hh + 1) / P.snap_every - 1 : -1;
-        if (P.variant == 1) {
-            if (wg < P.nslices) {
-                recurrence<ACC, kNT>(P, pick2(P.G, cur), pick2(P.rp, cur), h, nullptr, nullptr, cl,
-                                     nullptr, dl, pw, tpr);
-                for (int sl = wg; sl < P.nslices; sl += nb)
-                    update_margin_slice<DT, kNW>(P, sl, cl, h, true, h + 1, more, pick2(P.rp, nxt),
-                                                 red, xs, snap_row);
-            }
-            if (has_gram && more) gram_phase<DT>(P, pick2(P.G, nxt), h + 1, base, base + nb, lds);
-            if (more2) gather_rows<DT>(P, h + 2, gw, ngw);
-            if (!grid_barrier(P.flags, nb, spin)) return;
-        } else {
-            if (wg == 0) {
-                recurrence<ACC, kNT>(P, pick2(P.G, cur), pick2(P.rp, cur), h, nullptr, nullptr, P.c,
-                                     nullptr, dl, pw, tpr);
-            } else {
-                const int gw1 = gw - kNW, ngw1 = ngw - kNW;
-                if (has_gram && more)
-                    gram_phase<DT>(P, pick2(P.G, nxt), h + 1, base + 1, base + nb, lds);
-                if (more2) gather_rows<DT>(P, h + 2, gw1, ngw1);
-            }
-            if (!grid_barrier(P.flags, nb, spin)) return;
-            for (int sl = wg; sl < P.nslices; sl += nb)
-                update_margin_slice<DT, kNW>(P, sl, P.c, h, true, h + 1, more, pick2(P.rp, nxt), red,
-                                             xs, snap_row);
-            if (!grid_barrier(P.flags, nb, spin)) return;
-        }
-        if (snap && wg == 0 && threadIdx.x == 0 && P.t_hist)
-            P.t_hist[snap_row + 1] = (int64_t)wall_clock64();
-    }
-}
-
-template <int DT, typename ACC>
-__global__ __launch_bounds__(kNT) void k_fit(Dense P, unsigned long long spin) {
-    extern __shared__ __align__(16) unsigned char lds[];
-    fit_body<DT, ACC>(P, blockIdx.x, gridDim.x, spin, lds);
-}
-
 // Many problems in one cooperative launch: workgroup w runs problem
 // wgmap[w].x as member wgmap[w].y of that problem's group (table[p].gsize
 // workgroups, contiguous). Each problem keeps its own workspace and barrier.
@@ -192,9 +100,9 @@ __global__ __launch_bounds__(kNT) void k_fit_batch(const Dense* table, const int
     const Dense& P = table[__builtin_amdgcn_readfirstlane(me.x)];
     const int wg = __builtin_amdgcn_readfirstlane(me.y);
     if (P.recur64)
-        fit_body<DT, double>(P, wg, P.gsize, spin, lds);
+        fit_body<DT, double, false>(P, wg, P.gsize, spin, lds);
     else
-        fit_body<DT, float>(P, wg, P.gsize, spin, lds);
+        fit_body<DT, float, false>(P, wg, P.gsize, spin, lds);
 }
 
 // ------------------------------------------------------------------ host
@@ -243,57 +151,12 @@ __global__ __launch_bounds__(kNT) void k_rec_multi(Dense P, const float* G, cons
                                                    const float* y, float* c, float* delta_out,
                                                    unsigned long long spin) {
     extern __shared__ __align__(16) unsigned char lds[];
-    recurrence_multi<ACC, NV>(P, G, r, y, c, delta_out, P.pub, spin, lds);
+    recurrence_multi<ACC, NV>(P, G, r, y, c, delta_out, P.pub, spin, lds, (int)blockIdx.x);
 }
 
 template <typename ACC>
 size_t rec_lds(const Dense& P) {
     return (size_t)P.sb * sizeof(ACC) + (size_t)(P.s + 1) * sizeof(ACC);
-}
-
-template <int DT, typename ACC>
-casgd_status launch_fit_t(const Dense& P, const FitPlan& plan, hipStream_t st) {
-    const size_t lds = fit_lds_bytes(P.sb, P.s, (int)sizeof(ACC), slice_width<DT>());
-    auto kern = k_fit<DT, ACC>;
-    if (lds > 65536) {
-        set_error("fused kernel needs %zu bytes of LDS (s*b too large for it)", lds);
-        return CASGD_EUNSUPPORTED;
-    }
-    Dense Pc = P;
-    unsigned long long spin = plan.spin;
-    void* args[] = {&Pc, &spin};
-    CASGD_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(plan.grid),
-                                         dim3(kNT), args, (unsigned)lds, st));
-    return CASGD_OK;
-}
-
-template <int DT, typename ACC>
-int fit_max_grid(const Dense& P) {
-    const size_t lds = fit_lds_bytes(P.sb, P.s, (int)sizeof(ACC), slice_width<DT>());
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void*>(k_fit<DT, ACC>), kNT, lds) != hipSuccess)
-        return 0;
-    return per_cu * device_cus();
-}
-
-template <int DT>
-casgd_status dispatch_fit_dt(const Dense& P, const FitPlan& plan, hipStream_t st) {
-    return plan.recur64 ? launch_fit_t<DT, double>(P, plan, st) : launch_fit_t<DT, float>(P, plan, st);
-}
-
-template <int DT>
-int max_grid_dt(const Dense& P, int recur64) {
-    return recur64 ? fit_max_grid<DT, double>(P) : fit_max_grid<DT, float>(P);
-}
-
-int max_grid(const Dense& P, int dtype, int recur64) {
-    switch (dtype) {
-        case DT_F32: return max_grid_dt<DT_F32>(P, recur64);
-        case DT_BF16: return max_grid_dt<DT_BF16>(P, recur64);
-        case DT_F16: return max_grid_dt<DT_F16>(P, recur64);
-        default: return max_grid_dt<DT_FP8>(P, recur64);
-    }
 }
 
 }  // namespace
@@ -365,8 +228,8 @@ template <typename ACC, int NV>
 static casgd_status launch_rec_multi_t(const Dense& P, const float* G, const float* r,
                                        const float* y, float* c, float* delta_out,
                                        unsigned long long spin, hipStream_t st) {
-    constexpr int W = rec_window<NV>();
-    const int R = P.s - W - 1 > 0 ? P.s - W - 1 : 0;
+    static_assert(rec_window<NV>() == (NV <= 4 ? 2 : 1), "rec_helpers assumes this window");
+    const int R = rec_helpers(P.b, P.s);
     const size_t lds = (size_t)(P.sb + P.s + 1) * sizeof(ACC);
     Dense Pc = P;
     void* args[] = {&Pc, const_cast<float**>(&G), const_cast<float**>(&r), const_cast<float**>(&y),
@@ -456,6 +319,15 @@ casgd_status run_recurrence(const Dense& P, const float* G, const float* rp, uin
     return CASGD_OK;
 }
 
+static int fit_max_grid_dt(const Dense& P, int dtype, int recur64) {
+    switch (dtype) {
+        case DT_F32: return fit_max_grid_f32(P, recur64);
+        case DT_BF16: return fit_max_grid_bf16(P, recur64);
+        case DT_F16: return fit_max_grid_f16(P, recur64);
+        default: return fit_max_grid_fp8(P, recur64);
+    }
+}
+
 casgd_status plan_fit(const Dense& P, int dtype, const casgd_opts* o, int64_t H, FitPlan* plan) {
     const int64_t sb = P.sb;
     int prec = o ? o->recur_prec : 0;
@@ -464,8 +336,7 @@ casgd_status plan_fit(const Dense& P, int dtype, const casgd_opts* o, int64_t H,
         return CASGD_EINVAL;
     }
     plan->recur64 = prec == 64 || (prec == 0 && sb >= 512);
-    plan->exec_mode = (o && o->exec_mode) ? o->exec_mode
-                                           : (sb > 256 && rec_multi_ok(P) ? 2 : 1);
+    plan->exec_mode = (o && o->exec_mode) ? o->exec_mode : 1;
     if (plan->exec_mode != 1 && plan->exec_mode != 2) {
         set_error("exec_mode must be 0, 1 or 2 (got %d)", plan->exec_mode);
         return CASGD_EINVAL;
@@ -473,10 +344,17 @@ casgd_status plan_fit(const Dense& P, int dtype, const casgd_opts* o, int64_t H,
     plan->spin = (o && o->spin_limit > 0) ? (unsigned long long)o->spin_limit : (1ull << 24);
     // Strict block-lower Gram bytes read by each recurrence.
     const double gl_bytes = 4.0 * P.b * (double)P.b * P.s * (P.s - 1) / 2.0;
-    int variant = (o && o->fused_variant) ? o->fused_variant : (gl_bytes <= 256.0 * 1024 ? 1 : 2);
-    if (variant != 1 && variant != 2) {
-        set_error("fused_variant must be 0, 1 or 2 (got %d)", variant);
+    const bool multi_ok = rec_multi_ok(P) && P.s > 1;
+    int variant = (o && o->fused_variant)
+                      ? o->fused_variant
+                      : (multi_ok && sb > 256 ? 3 : (gl_bytes <= 256.0 * 1024 ? 1 : 2));
+    if (variant < 1 || variant > 3) {
+        set_error("fused_variant must be 0, 1, 2 or 3 (got %d)", variant);
         return CASGD_EINVAL;
+    }
+    if (variant == 3 && !multi_ok) {
+        set_error("fused_variant 3 needs b = 16, 32, 64 or 128 and s > 1");
+        return CASGD_EUNSUPPORTED;
     }
     plan->variant = variant;
     plan->grid = 0;
@@ -486,17 +364,19 @@ casgd_status plan_fit(const Dense& P, int dtype, const casgd_opts* o, int64_t H,
         plan->exec_mode = 2;  // the fused kernel cannot hold this recurrence in LDS
         return CASGD_OK;
     }
-    const int maxg = max_grid(P, dtype, plan->recur64);
+    const int maxg = fit_max_grid_dt(P, dtype, plan->recur64);
     if (maxg <= 0) {
         plan->exec_mode = 2;
         return CASGD_OK;
     }
     const int units = P.s > 1 ? (P.gna == 4 ? P.gt : 2 * P.gt) * P.ksplit : 0;
-    int want = std::max(P.nslices, units + (variant == 2 ? 1 : 0));
-    want = std::max(want, variant == 2 ? 2 : 1);
+    // workgroups that run the recurrence while the others build the next Gram
+    const int nrec = variant == 3 ? 1 + rec_helpers(P.b, P.s) : (variant == 2 ? 1 : 0);
+    int want = std::max(P.nslices, units + nrec);
+    want = std::max(want, nrec + 1);
     if (o && o->grid_blocks > 0) want = o->grid_blocks;
     plan->grid = std::min(want, maxg);
-    if (variant == 2 && plan->grid < 2) plan->exec_mode = 2;
+    if (plan->grid < nrec + 1) plan->exec_mode = 2;
     (void)H;
     return CASGD_OK;
 }
@@ -512,6 +392,9 @@ casgd_status run_fit(const Dense& P, int dtype, uint64_t h0, int64_t H, const Fi
         // Barrier words start from zero for every fused launch.
         if ((rc = run_zero(P.flags + FLAG_BAR_COUNT, FLAG_WORDS - FLAG_BAR_COUNT, st)) != CASGD_OK)
             return rc;
+        if (plan.variant == 3 &&
+            (rc = run_zero(reinterpret_cast<unsigned*>(P.pub), (int64_t)P.sb * 8, st)) != CASGD_OK)
+            return rc;
         Dense Q = P;
         Q.h0 = h0;
         Q.H = H;
@@ -520,10 +403,10 @@ casgd_status run_fit(const Dense& P, int dtype, uint64_t h0, int64_t H, const Fi
         Q.recur64 = plan.recur64;
         Q.tpr = recurrence_tpr(kNT, P.b);
         switch (dtype) {
-            case DT_F32: return dispatch_fit_dt<DT_F32>(Q, plan, st);
-            case DT_BF16: return dispatch_fit_dt<DT_BF16>(Q, plan, st);
-            case DT_F16: return dispatch_fit_dt<DT_F16>(Q, plan, st);
-            default: return dispatch_fit_dt<DT_FP8>(Q, plan, st);
+            case DT_F32: return launch_fit_f32(Q, plan, st);
+            case DT_BF16: return launch_fit_bf16(Q, plan, st);
+            case DT_F16: return launch_fit_f16(Q, plan, st);
+            default: return launch_fit_fp8(Q, plan, st);
         }
     }
     // Stream-ordered: gather(h0), margin(h0); then per outer: gram(h),

@@ -268,14 +268,17 @@ __device__ __forceinline__ void gram_unit(const Dense& P, float* Gout, uint64_t 
         r.w[0] = q[0]; r.w[1] = q[1]; r.w[2] = q[2]; r.w[3] = q[3];
         return r;
     };
-    // Ping-pong operand buffers: the loads of step k+1 are in flight while the
-    // MFMAs of step k run.
-    V16 A0[NA], B0[4], A1[NA], B1[4];
+    // Three operand buffers: the loads of steps k+1 and k+2 are in flight
+    // while the MFMAs of step k run. Every load is unconditional (positions
+    // past the end are clamped to the last step and not used): a conditional
+    // load would become a branch whose join waits for it.
+    V16 A0[NA], B0[4], A1[NA], B1[4], A2[NA], B2[4];
     auto load = [&](V16 (&Av)[NA], V16 (&Bv)[4], int64_t k) {
+        const int64_t kk = k < k1 ? k : k1 - KSTEP;
 #pragma unroll
-        for (int a = 0; a < NA; ++a) Av[a] = ld16(ra[a], k);
+        for (int a = 0; a < NA; ++a) Av[a] = ld16(ra[a], kk);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) Bv[c] = ld16(rb[c], k);
+        for (int c = 0; c < 4; ++c) Bv[c] = ld16(rb[c], kk);
     };
     auto mma = [&](const V16 (&Av)[NA], const V16 (&Bv)[4]) {
         // q outermost: NA*4 independent accumulators between dependent MFMAs
@@ -286,18 +289,25 @@ __device__ __forceinline__ void gram_unit(const Dense& P, float* Gout, uint64_t 
 #pragma unroll
                 for (int c = 0; c < 4; ++c) mfma_q<DT>(Av[a], Bv[c], q, acc[a][c]);
     };
-    // Pairs of K steps with a single loop exit (a second exit would make the
+    // Triples of K steps with a single loop exit (a second exit would make the
     // compiler move the accumulators out of and back into AGPRs every step).
-    int64_t k = k0;
-    if (k0 < k1) load(A0, B0, k0);
+    if (k0 < k1) {
+        int64_t k = k0;
+        load(A0, B0, k0);
+        load(A1, B1, k0 + KSTEP);
 #pragma unroll 1
-    for (; k + 2 * KSTEP <= k1; k += 2 * KSTEP) {
-        load(A1, B1, k + KSTEP);
-        mma(A0, B0);
-        if (k + 2 * KSTEP < k1) load(A0, B0, k + 2 * KSTEP);
-        mma(A1, B1);
+        for (; k + 3 * KSTEP <= k1; k += 3 * KSTEP) {
+            load(A2, B2, k + 2 * KSTEP);
+            mma(A0, B0);
+            load(A0, B0, k + 3 * KSTEP);
+            mma(A1, B1);
+            load(A1, B1, k + 4 * KSTEP);
+            mma(A2, B2);
+        }
+        // 0, 1 or 2 steps remain: A0 holds step k, A1 step k + KSTEP
+        if (k < k1) mma(A0, B0);
+        if (k + KSTEP < k1) mma(A1, B1);
     }
-    if (k < k1) mma(A0, B0);
 
     // Cross-wave reduction, one sub-tile row at a time: wave w sums sub-tile
     // (a, w) over the four waves in wave order.

@@ -1,0 +1,191 @@
+// The fused persistent fit: one cooperative launch runs every outer
+// iteration, with phases separated by the bounded grid barrier. Included by
+// one translation unit per storage type (fit_<type>.hip) and by the batched
+// launch.
+#pragma once
+
+#include "internal.hpp"
+#include "recurrence.hpp"
+
+namespace casgd {
+
+// Margins of outer iteration h from the slices' partial sums: eight lanes per
+// row, lane e adding slices e, e+8, ... in order, then a fixed tree over the
+// eight lanes; times the row scale. Threads gtid of nthreads (multiples of 8).
+__device__ __forceinline__ void reduce_margins(const Dense& P, const float* rp, uint64_t h,
+                                               float* r_out, int gtid, int nthreads) {
+    const float* sI = pick3(P.sI, slot_of(h));
+    const int e = gtid & 7;
+    // the eight lanes of a group share t, so they run the loop together
+    for (int t = gtid >> 3; t < P.sb; t += nthreads >> 3) {
+        float a = 0.f;
+#pragma unroll 8
+        for (int sl = e; sl < P.nslices; sl += 8) a += rp[(int64_t)sl * P.sb + t];
+        a += shfl_xor(a, 1);
+        a += shfl_xor(a, 2);
+        a += shfl_xor(a, 4);
+        if (e == 0) r_out[t] = a * sI[t];
+    }
+}
+
+// The recurrence workgroup of rank `rank` (0 = chain, 1.. = helpers) for the
+// problem's b (16, 32, 64 or 128).
+template <typename ACC>
+__device__ __forceinline__ void rec_multi_rank(const Dense& P, const float* G, const float* r,
+                                               const float* y, float* c, unsigned long long spin,
+                                               unsigned char* lds, int rank) {
+    switch (P.b) {
+        case 16: recurrence_multi<ACC, 1>(P, G, r, y, c, nullptr, P.pub, spin, lds, rank); break;
+        case 32: recurrence_multi<ACC, 2>(P, G, r, y, c, nullptr, P.pub, spin, lds, rank); break;
+        case 64: recurrence_multi<ACC, 4>(P, G, r, y, c, nullptr, P.pub, spin, lds, rank); break;
+        default: recurrence_multi<ACC, 8>(P, G, r, y, c, nullptr, P.pub, spin, lds, rank); break;
+    }
+}
+
+// LDS bytes of the persistent kernel: recurrence history, decay powers, the
+// workgroup's copy of c (variant 1), and the update's reduction buffers.
+__host__ __device__ inline size_t fit_lds_bytes(int sb, int s, int acc_bytes, int kw) {
+    size_t off = (size_t)sb * acc_bytes;
+    off += (size_t)(s + 1) * acc_bytes;
+    off = (off + 15) & ~(size_t)15;
+    off += (size_t)sb * 4;                // c copy
+    off += (size_t)kNW * kw * 4 + kw * 4; // red + xs
+    // the Gram phase reuses the same memory (phases never overlap in a workgroup)
+    return s > 1 && off < kGramLds ? kGramLds : off;
+}
+
+// One problem's whole fit on the workgroups wg = 0 .. nb-1 of its group (the
+// grid, or one group of a batched launch), with the group's own barrier.
+template <int DT, typename ACC, bool MULTI>
+__device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigned long long spin,
+                                         unsigned char* lds) {
+    constexpr int KW = slice_width<DT>();
+    ACC* dl = reinterpret_cast<ACC*>(lds);
+    ACC* pw = dl + P.sb;
+    size_t off = (size_t)P.sb * sizeof(ACC) + (size_t)(P.s + 1) * sizeof(ACC);
+    off = (off + 15) & ~(size_t)15;
+    float* cl = reinterpret_cast<float*>(lds + off);
+    float* red = cl + P.sb;
+    float* xs = red + kNW * KW;
+
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool has_gram = P.s > 1;
+    // physical workgroup range of this problem (the Gram phase maps K splits
+    // to XCDs by physical index)
+    const int base = (int)blockIdx.x - wg;
+    const uint64_t h0 = P.h0;
+    const int64_t H = P.H;
+    const int tpr = P.tpr;
+
+    if (threadIdx.x == 0 && wg == 0 && P.t_hist) P.t_hist[0] = (int64_t)wall_clock64();
+    const int gw = wg * kNW + wave, ngw = nb * kNW;
+
+    // Prologue: gather the rows of h0 and h0+1; then the Gram of h0 and the
+    // margins of h0 from the incoming x (variant 3: reduced to P.r).
+    gather_rows<DT>(P, h0, gw, ngw);
+    if (H > 1) gather_rows<DT>(P, h0 + 1, gw, ngw);
+    if (!grid_barrier(P.flags, wg, nb, spin)) return;
+    if (has_gram) gram_phase<DT>(P, P.G[0], h0, base, base + nb, lds);
+    for (int sl = wg; sl < P.nslices; sl += nb)
+        update_margin_slice<DT, kNW>(P, sl, nullptr, 0, false, h0, true, P.rp[0], red, xs, -1);
+    if (!grid_barrier(P.flags, wg, nb, spin)) return;
+    if (MULTI && P.variant == 3) {
+        reduce_margins(P, P.rp[0], h0, P.r, wg * kNT + (int)threadIdx.x, nb * kNT);
+        if (!grid_barrier(P.flags, wg, nb, spin)) return;
+    }
+
+    for (int64_t hh = 0; hh < H; ++hh) {
+        const uint64_t h = h0 + (uint64_t)hh;
+        const int cur = (int)(hh & 1), nxt = cur ^ 1;
+        const bool more = hh + 1 < H;
+        const bool more2 = hh + 2 < H;
+        const bool snap = P.snap_every > 0 && ((hh + 1) % P.snap_every) == 0;
+        const int64_t snap_row = snap ? (hh + 1) / P.snap_every - 1 : -1;
+        if (MULTI && P.variant == 3) {
+            // recurrence of h on workgroups 0 .. nrec-1 (chain + helpers);
+            // Gram of h+1 and rows of h+2 on the others
+            const int nrec = 1 + rec_helpers(P.b, P.s);
+            if (wg < nrec) {
+                rec_multi_rank<ACC>(P, pick2(P.G, cur), P.r, pick3(P.yI, slot_of(h)), P.c, spin, lds,
+                                    wg);
+            } else {
+                if (has_gram && more)
+                    gram_phase<DT>(P, pick2(P.G, nxt), h + 1, base + nrec, base + nb, lds);
+                if (more2) gather_rows<DT>(P, h + 2, gw - nrec * kNW, ngw - nrec * kNW);
+            }
+            if (!grid_barrier(P.flags, wg, nb, spin)) return;
+            for (int sl = wg; sl < P.nslices; sl += nb)
+                update_margin_slice<DT, kNW>(P, sl, P.c, h, true, h + 1, more, pick2(P.rp, nxt), red,
+                                             xs, snap_row);
+            if (!grid_barrier(P.flags, wg, nb, spin)) return;
+            if (more) {
+                reduce_margins(P, pick2(P.rp, nxt), h + 1, P.r, wg * kNT + (int)threadIdx.x, nb * kNT);
+                if (!grid_barrier(P.flags, wg, nb, spin)) return;
+            }
+        } else if (P.variant == 1) {
+            if (wg < P.nslices) {
+                recurrence<ACC, kNT>(P, pick2(P.G, cur), pick2(P.rp, cur), h, nullptr, nullptr, cl,
+                                     nullptr, dl, pw, tpr);
+                for (int sl = wg; sl < P.nslices; sl += nb)
+                    update_margin_slice<DT, kNW>(P, sl, cl, h, true, h + 1, more, pick2(P.rp, nxt),
+                                                 red, xs, snap_row);
+            }
+            if (has_gram && more) gram_phase<DT>(P, pick2(P.G, nxt), h + 1, base, base + nb, lds);
+            if (more2) gather_rows<DT>(P, h + 2, gw, ngw);
+            if (!grid_barrier(P.flags, wg, nb, spin)) return;
+        } else {
+            if (wg == 0) {
+                recurrence<ACC, kNT>(P, pick2(P.G, cur), pick2(P.rp, cur), h, nullptr, nullptr, P.c,
+                                     nullptr, dl, pw, tpr);
+            } else {
+                const int gw1 = gw - kNW, ngw1 = ngw - kNW;
+                if (has_gram && more)
+                    gram_phase<DT>(P, pick2(P.G, nxt), h + 1, base + 1, base + nb, lds);
+                if (more2) gather_rows<DT>(P, h + 2, gw1, ngw1);
+            }
+            if (!grid_barrier(P.flags, wg, nb, spin)) return;
+            for (int sl = wg; sl < P.nslices; sl += nb)
+                update_margin_slice<DT, kNW>(P, sl, P.c, h, true, h + 1, more, pick2(P.rp, nxt), red,
+                                             xs, snap_row);
+            if (!grid_barrier(P.flags, wg, nb, spin)) return;
+        }
+        if (snap && wg == 0 && threadIdx.x == 0 && P.t_hist)
+            P.t_hist[snap_row + 1] = (int64_t)wall_clock64();
+    }
+}
+
+template <int DT, typename ACC>
+__global__ __launch_bounds__(kNT) void k_fit(Dense P, unsigned long long spin) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    fit_body<DT, ACC, true>(P, blockIdx.x, gridDim.x, spin, lds);
+}
+
+
+template <int DT, typename ACC>
+inline casgd_status launch_fit_t(const Dense& P, const FitPlan& plan, hipStream_t st) {
+    const size_t lds = fit_lds_bytes(P.sb, P.s, (int)sizeof(ACC), slice_width<DT>());
+    auto kern = k_fit<DT, ACC>;
+    if (lds > 65536) {
+        set_error("fused kernel needs %zu bytes of LDS (s*b too large for it)", lds);
+        return CASGD_EUNSUPPORTED;
+    }
+    Dense Pc = P;
+    unsigned long long spin = plan.spin;
+    void* args[] = {&Pc, &spin};
+    CASGD_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(plan.grid),
+                                         dim3(kNT), args, (unsigned)lds, st));
+    return CASGD_OK;
+}
+
+template <int DT, typename ACC>
+inline int fit_max_grid(const Dense& P) {
+    const size_t lds = fit_lds_bytes(P.sb, P.s, (int)sizeof(ACC), slice_width<DT>());
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void*>(k_fit<DT, ACC>), kNT, lds) != hipSuccess)
+        return 0;
+    return per_cu * device_cus();
+}
+
+
+}  // namespace casgd

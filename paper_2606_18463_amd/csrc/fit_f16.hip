@@ -1,0 +1,15 @@
+// Fused persistent fit for f16 storage.
+#include "fit.hpp"
+
+namespace casgd {
+
+casgd_status launch_fit_f16(const Dense& P, const FitPlan& plan, hipStream_t st) {
+    return plan.recur64 ? launch_fit_t<DT_F16, double>(P, plan, st)
+                        : launch_fit_t<DT_F16, float>(P, plan, st);
+}
+
+int fit_max_grid_f16(const Dense& P, int recur64) {
+    return recur64 ? fit_max_grid<DT_F16, double>(P) : fit_max_grid<DT_F16, float>(P);
+}
+
+}  // namespace casgd

@@ -60,6 +60,14 @@ casgd_status run_zero(unsigned* p, int64_t words, hipStream_t st);
 casgd_status run_fit_batch(const Dense* table_dev, const int2* wgmap_dev, int grid, int dtype,
                            size_t lds, unsigned long long spin, hipStream_t st);
 int batch_max_grid(int dtype, size_t lds);
+casgd_status launch_fit_f32(const Dense& P, const FitPlan& plan, hipStream_t st);
+casgd_status launch_fit_bf16(const Dense& P, const FitPlan& plan, hipStream_t st);
+casgd_status launch_fit_f16(const Dense& P, const FitPlan& plan, hipStream_t st);
+casgd_status launch_fit_fp8(const Dense& P, const FitPlan& plan, hipStream_t st);
+int fit_max_grid_f32(const Dense& P, int recur64);
+int fit_max_grid_bf16(const Dense& P, int recur64);
+int fit_max_grid_f16(const Dense& P, int recur64);
+int fit_max_grid_fp8(const Dense& P, int recur64);
 size_t fit_lds(const Dense& P, int dtype, int recur64);
 
 int device_cus();

@@ -92,8 +92,14 @@ __device__ __forceinline__ ACC dot_nv(const float4 (&g)[NV], const ACC* d) {
     return a;
 }
 
-// One launch of the recurrence for b = 16 * NV, kNT threads per workgroup,
-// 1 + max(0, s - W - 1) workgroups, all resident. Thread layout: four
+// Helper workgroups of the recurrence for block size b (b = 16, 32, 64, 128).
+__host__ __device__ inline int rec_helpers(int b, int s) {
+    const int w = b <= 64 ? 2 : 1;   // rec_window<b / 16>()
+    return s - w - 1 > 0 ? s - w - 1 : 0;
+}
+
+// The recurrence for b = 16 * NV on 1 + rec_helpers(b, s) workgroups of kNT
+// threads, all resident; `rank` is this workgroup's index among them. Thread layout: four
 // threads per row (sub = tid % 4 owns columns [sub*b/4, (sub+1)*b/4) of
 // every column block), 64 rows per pass. r: reduced margins (row scales
 // applied); y: labels; c, delta_out: outputs; pub: 2 * sb * pub_words
@@ -101,7 +107,7 @@ __device__ __forceinline__ ACC dot_nv(const float4 (&g)[NV], const ACC* d) {
 template <typename ACC, int NV, int W = rec_window<NV>()>
 __device__ void recurrence_multi(const Dense& P, const float* G, const float* r, const float* y,
                                  float* c, float* delta_out, unsigned long long* pub,
-                                 unsigned long long spin, unsigned char* lds) {
+                                 unsigned long long spin, unsigned char* lds, int rank) {
     constexpr int PASSES = rec_passes<NV>();
     constexpr int PW = pub_words<ACC>();
     const int b = 16 * NV, s = P.s, sb = P.sb;
@@ -122,7 +128,7 @@ __device__ void recurrence_multi(const Dense& P, const float* G, const float* r,
     __syncthreads();
     const int R = s - W - 1 > 0 ? s - W - 1 : 0;
 
-    if (blockIdx.x == 0) {
+    if (rank == 0) {
         // ------------------------------------------------------------ main
         // Step j uses the near blocks and far-sum words loaded during step
         // j-1 (two register sets, alternating), so their latency overlaps a
@@ -215,7 +221,7 @@ __device__ void recurrence_multi(const Dense& P, const float* G, const float* r,
     }
 
     // ------------------------------------------------------------ helpers
-    const int jh = W + (int)blockIdx.x;     // the row block this helper owns
+    const int jh = W + rank;                 // the row block this helper owns
     if (jh >= s) return;
     ACC* di = dl;                            // deltas of the current column block
     ACC acc[PASSES];

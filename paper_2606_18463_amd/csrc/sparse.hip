@@ -72,13 +72,13 @@ __global__ __launch_bounds__(kNT) void k_sparse_fit(Sparse S, uint64_t h0, int64
     // Prologue: rows of h0 and h0+1; buckets and Gram of h0; margins of h0.
     sparse_gather(S, h0, gw, ngw, hrow);
     if (H > 1) sparse_gather(S, h0 + 1, gw, ngw, hrow);
-    if (!grid_barrier(S.flags, nb, spin)) return;
+    if (!grid_barrier(S.flags, wg, nb, spin)) return;
     sparse_bucket(S, h0, gtid, nthr);
     gram_phase<DT_F32>(S.gram, spick2(S.G, (int)(h0 & 1)), h0, 0, nb, lds);
-    if (!grid_barrier(S.flags, nb, spin)) return;
+    if (!grid_barrier(S.flags, wg, nb, spin)) return;
     sparse_gram_tail(S, h0, spick2(S.G, (int)(h0 & 1)), gtid, nthr);
     sparse_margins(S, h0, gw, ngw);
-    if (!grid_barrier(S.flags, nb, spin)) return;
+    if (!grid_barrier(S.flags, wg, nb, spin)) return;
 
     for (int64_t hh = 0; hh < H; ++hh) {
         const uint64_t h = h0 + (uint64_t)hh;
@@ -98,13 +98,13 @@ __global__ __launch_bounds__(kNT) void k_sparse_fit(Sparse S, uint64_t h0, int64
             }
             if (more2) sparse_gather(S, h + 2, w0, nw, hrow);
         }
-        if (!grid_barrier(S.flags, nb, spin)) return;
+        if (!grid_barrier(S.flags, wg, nb, spin)) return;
         sparse_update(S, h, gw, ngw, gtid, nthr, snap_row);
         if (more) sparse_gram_tail(S, h + 1, spick2(S.G, (int)((h + 1) & 1)), gtid, nthr);
-        if (!grid_barrier(S.flags, nb, spin)) return;
+        if (!grid_barrier(S.flags, wg, nb, spin)) return;
         if (more) sparse_margins(S, h + 1, gw, ngw);
         sparse_clear_buckets(S, h, gtid, nthr);
-        if (!grid_barrier(S.flags, nb, spin)) return;
+        if (!grid_barrier(S.flags, wg, nb, spin)) return;
         if (snap && wg == 0 && threadIdx.x == 0 && S.t_hist)
             S.t_hist[snap_row + 1] = (int64_t)wall_clock64();
     }

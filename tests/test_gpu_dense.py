@@ -212,10 +212,14 @@ def test_stream_ordered_multi_workgroup_recurrence(cg, b, s, prec):
     xg = _fit(cg, X, y, np.zeros(136, np.float32), 0.5, 1e-4, b, s, 9, H, exec_mode=2,
               recur_prec=prec)
     xf = _fit(cg, X, y, np.zeros(136, np.float32), 0.5, 1e-4, b, s, 9, H, exec_mode=1,
-              recur_prec=prec)
+              fused_variant=2, recur_prec=prec)
+    x3 = _fit(cg, X, y, np.zeros(136, np.float32), 0.5, 1e-4, b, s, 9, H, exec_mode=1,
+              fused_variant=3, recur_prec=prec)
     xo = R.casgd(p.X, p.y, np.zeros(136), 0.5, 1e-4, b, s, 9, 0, H)
-    assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) < 1e-4
-    assert np.linalg.norm(xg - xf) / np.linalg.norm(xo) < 1e-4
+    for xv in (xg, xf, x3):
+        assert np.linalg.norm(xv - xo) / np.linalg.norm(xo) < 1e-4
+    # the fused variant 3 runs the same recurrence and margin reduction
+    assert np.linalg.norm(x3 - xg) / np.linalg.norm(xo) < 1e-6
 
 
 def test_exec_modes_bitwise_equal(cg, c1data):
