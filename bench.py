@@ -266,6 +266,157 @@ def measured_traffic(name: str, outer_per_launch: int):
     return round(d["hbm_bytes_per_outer"] * outer_per_launch)
 
 
+def c4_bench(cg, steps: int, warmup: int):
+    """Sparse CSR regularisation path: 10^6 x 2^17, ~50 nnz/row (Zipf 1.1), 32
+    lambdas in one persistent launch sharing every sampled block and its Gram,
+    b = 128, s = 16, FP32."""
+    import torch
+    from workloads import lambda_path_c4, sparse_c4
+    t = time.perf_counter()
+    p = sparse_c4(SEED)
+    log(f"[c4] generated CSR {p.m}x{p.n}, {p.values.size} nnz in {time.perf_counter() - t:.1f}s")
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    X = cg.csr_matrix(dev(p.row_ptr), dev(p.col_idx), dev(p.values), p.n)
+    Xt = cg.csr_matrix(dev(p.test_row_ptr), dev(p.test_col_idx), dev(p.test_values), p.n)
+    y, yt = dev(p.y), dev(p.y_test)
+    lams = [float(v) for v in lambda_path_c4()]
+    L, b, s = len(lams), 128, 16
+    ws = cg.casgd_sparse_prepare(X, b, s, L)
+    # step size: best lane's test loss after a quarter epoch, eta in 2^k
+    quarter = max(1, p.m // (4 * b * s))
+    best = None
+    for k in range(0, 10):
+        eta = 2.0 ** k
+        xl = torch.zeros(p.n, L, device="cuda")
+        cg.casgd_fit_path(X, y, xl, lams, eta, b, s, SEED, 0, quarter, ws=ws)
+        cg.casgd_check(ws)
+        loss = float(cg.casgd_logloss(Xt, yt, xl.t().contiguous()).min())
+        log(f"[c4] eta={eta:g}: best-lane test loss {loss:.6f}")
+        if math.isfinite(loss) and (best is None or loss < best[0]):
+            best = (loss, eta)
+    eta = best[1]
+    xl = torch.zeros(p.n, L, device="cuda")
+    stream = torch.cuda.current_stream()
+    cg.casgd_fit_path(X, y, xl, lams, eta, b, s, SEED, 0, warmup, ws=ws, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    cg.casgd_fit_path(X, y, xl, lams, eta, b, s, SEED, warmup, steps, ws=ws, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    cg.casgd_check(ws)
+    ms = e0.elapsed_time(e1)
+    losses = cg.casgd_logloss(Xt, yt, xl.t().contiguous()).cpu().numpy()
+    # algorithmic bytes of one outer iteration, from one sampled block: its
+    # nonzeros (value + column) and row offsets once, and the lane rows of x
+    # for the distinct columns it touches, read and written
+    idx = cg.casgd_sample_indices(SEED, warmup * s * b, s * b, p.m).cpu().numpy()
+    nnz = int((p.row_ptr[idx + 1] - p.row_ptr[idx]).sum())
+    cols = np.unique(np.concatenate([p.col_idx[p.row_ptr[i]:p.row_ptr[i + 1]] for i in idx]))
+    by = nnz * 8 + 16 * s * b + cols.size * L * 8
+    ups = s * steps / (ms * 1e-3)
+    ach = by * steps / (ms * 1e-3) / 1e9
+    return {"metric": "SGD updates/s per lambda lane (sparse CSR lambda path)",
+            "value": round(ups, 1), "unit": "SGD updates/s", "lanes": L,
+            "lane_updates_per_s": round(ups * L, 1), "steps": steps, "warmup": warmup,
+            "ms_per_step": round(ms / steps, 6), "eta": eta, "dtype": "f32",
+            "config": {"workload": f"sparse CSR {p.m}x{p.n}, ~50 nnz/row Zipf(1.1), "
+                                   f"{L} lambdas 1e-7..1e-2, b={b}, s={s}"},
+            "roofline": {"bound": "hbm", "achieved": round(ach, 2), "peak": PEAK["hbm_GBps"],
+                         "unit": "GB/s", "frac": round(ach / PEAK["hbm_GBps"], 5),
+                         "algorithmic_bytes_per_outer": by, "sampled_nnz": nnz,
+                         "distinct_columns": int(cols.size)},
+            "test_loss_by_lane": [round(float(v), 6) for v in losses]}
+
+
+def c5_bench(cg, n_train: int, n_eval: int, epochs: float = 2.0):
+    """Learned diagonal preconditioner on uneven dense problems (BF16 X, s = 16,
+    b = 64): MLP trained by the library's kernels on targets from plain runs,
+    then applied to unseen problems; both methods run batched (one launch per
+    chunk of outer iterations for all problems) and are compared by test loss
+    over the same budget."""
+    import torch
+    from paper_2606_18463_amd import learned as Lm
+    from workloads import uneven_problem, uneven_problem_specs
+    b, s, lam = 64, 16, 1e-5
+    rng = dict(m_range=(1e4, 5e4), n_range=(128, 1024), spread_range=(1.0, 1e3))
+    t0 = time.perf_counter()
+    stats, tds, tetas = [], [], []
+    for sp in uneven_problem_specs(n_train, 101, **rng):
+        dp = Lm.upload(uneven_problem(sp), dtype=cg.BF16)
+        t_d, log_eta, _ = Lm.targets(dp, lam, b, s, SEED, epochs=1.0)
+        stats.append(cg.casgd_colstats(Lm.stored(dp)))
+        tds.append(t_d)
+        tetas.append(log_eta)
+        del dp
+    t_targets = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    model, hist = Lm.train(stats, tds, tetas, steps=1500, lr=1e-2, log_every=500)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    log(f"[c5] targets for {n_train} problems in {t_targets:.1f}s, MLP trained in {t_train:.1f}s: {hist}")
+
+    evals = []
+    for sp in uneven_problem_specs(n_eval, 202, **rng):
+        dp = Lm.upload(uneven_problem(sp), dtype=cg.BF16)
+        H = max(8, int(epochs * dp.m / (b * s)))
+        Xp = Lm.stored(dp)
+        eta_p = Lm.best_eta(Xp, dp.y, dp.Xt, dp.yt, dp.n, lam, b, s, SEED, max(2, H // 4))
+        q, eta_l = Lm.predict(model, Xp)
+        evals.append(dict(dp=dp, H=H, Xp=Xp, eta_p=eta_p, Xl=Lm.stored(dp, q),
+                          Xtl=Lm.stored_test(dp, q), eta_l=eta_l))
+    chunks = 8
+    curves = {"plain": [], "learned": []}
+    times = {"plain": 0.0, "learned": 0.0}
+    for kind in ("plain", "learned"):
+        xs = [torch.zeros(e["dp"].n, device="cuda") for e in evals]
+        wss = [None] * len(evals)
+        per = []
+        for c in range(chunks):
+            batch = []
+            for i, e in enumerate(evals):
+                h0 = e["H"] * c // chunks
+                h1 = e["H"] * (c + 1) // chunks
+                batch.append(dict(X=e["Xp"] if kind == "plain" else e["Xl"], y=e["dp"].y, x=xs[i],
+                                  eta=e["eta_p"] if kind == "plain" else e["eta_l"], lam=lam,
+                                  b=b, s=s, seed=SEED, outer_begin=h0, n_outer=h1 - h0, ws=wss[i]))
+            torch.cuda.synchronize()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            wss = cg.casgd_fit_batch(batch)
+            ev1.record()
+            torch.cuda.synchronize()
+            times[kind] += ev0.elapsed_time(ev1) * 1e-3
+            for w in wss:
+                cg.casgd_check(w)
+            per.append([float(cg.casgd_logloss(e["dp"].Xt if kind == "plain" else e["Xtl"],
+                                               e["dp"].yt, xs[i])) for i, e in enumerate(evals)])
+        curves[kind] = np.array(per)      # chunks x problems
+    final_p, final_l = curves["plain"][-1], curves["learned"][-1]
+    rows = []
+    for i, e in enumerate(evals):
+        target = final_p[i] * (1 + TARGET_GAP)
+        hit = np.nonzero(curves["learned"][:, i] <= target)[0]
+        rows.append({"m": e["dp"].m, "n": e["dp"].n, "eta_plain": e["eta_p"],
+                     "eta_learned": round(e["eta_l"], 4),
+                     "final_loss_plain": round(float(final_p[i]), 6),
+                     "final_loss_learned": round(float(final_l[i]), 6),
+                     "budget_fraction_learned_to_plain_final": None if hit.size == 0
+                     else round((int(hit[0]) + 1) / chunks, 3)})
+    frac = [r["budget_fraction_learned_to_plain_final"] for r in rows]
+    reached = [f for f in frac if f is not None]
+    return {"metric": "learned diagonal preconditioner vs plain CA-SGD (uneven problems, batched)",
+            "train_problems": n_train, "eval_problems": n_eval, "storage": "bf16", "b": b, "s": s,
+            "budget_epochs": epochs, "mlp_loss": hist,
+            "seconds_batched_plain": round(times["plain"], 4),
+            "seconds_batched_learned": round(times["learned"], 4),
+            "learned_better_final_loss": int(np.sum(final_l < final_p)),
+            "median_budget_fraction_to_plain_final": None if not reached
+            else float(np.median(reached)),
+            "learned_reaches_plain_final": len(reached), "problems": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -286,6 +437,10 @@ def main():
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--source-hash", action="store_true")
+    ap.add_argument("--c4", action="store_true", help="sparse lambda-path workload only")
+    ap.add_argument("--c5", action="store_true", help="learned preconditioner workload only")
+    ap.add_argument("--c5-train", type=int, default=64)
+    ap.add_argument("--c5-eval", type=int, default=16)
     args = ap.parse_args()
     if args.source_hash:
         print(sources_hash())
@@ -303,6 +458,13 @@ def main():
     cg._lib.load()
     if args.copy_calib:
         copy_calibration()
+        return
+    if args.c5:
+        print(json.dumps(c5_bench(cg, args.c5_train, args.c5_eval)), flush=True)
+        return
+    if args.c4:
+        K = args.steps if args.steps is not None else 64
+        print(json.dumps(c4_bench(cg, K, args.warmup if args.warmup is not None else 8)), flush=True)
         return
 
     s, b, n, dtype = args.s, B_C2, args.n, args.dtype

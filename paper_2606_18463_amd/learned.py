@@ -27,7 +27,7 @@ import numpy as np
 
 import paper_2606_18463_amd as cg
 
-ETA_GRID = [2.0 ** k for k in range(-3, 6)]
+ETA_GRID = [2.0 ** k for k in range(-3, 9)]
 
 
 @dataclass
