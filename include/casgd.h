@@ -133,6 +133,18 @@ typedef struct {
      *   number that can be resident). */
     int32_t fused_variant;
     int32_t grid_blocks;
+    /* Phase clock of the fused kernel (measurement support; NULL = off):
+     * device, int64, 8 words per outer iteration for the first
+     * phase_trace_outer outer iterations, device wall clock (100 MHz ticks)
+     * when, in outer iteration k, [8k+0] workgroup 0 starts the first phase,
+     * [8k+1] workgroup 0 finishes it (its recurrence), [8k+2] the first
+     * Gram workgroup and [8k+6] the last workgroup finish it, [8k+3]
+     * workgroup 0 leaves the following barrier, [8k+4] finishes its update
+     * slices, [8k+5] leaves the next barrier, [8k+7] the last workgroup
+     * finishes its second-phase work. Words of phases a variant lacks stay
+     * untouched. */
+    int64_t *phase_trace;
+    int64_t phase_trace_outer;
 } casgd_opts;
 
 const char *casgd_status_string(casgd_status st);

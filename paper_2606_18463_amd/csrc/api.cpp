@@ -308,6 +308,10 @@ static casgd_status make_dense(const casgd_matrix* X, const float* y, float* x, 
         P->x_hist = o->x_history;
         P->t_hist = o->t_history;
     }
+    if (o && o->phase_trace && o->phase_trace_outer > 0) {
+        P->ptrace = o->phase_trace;
+        P->ptrace_outer = o->phase_trace_outer;
+    }
     return CASGD_OK;
 }
 

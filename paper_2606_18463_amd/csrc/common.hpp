@@ -179,13 +179,18 @@ __device__ __forceinline__ void lds_barrier() {
 enum : int {
     FLAG_NONFINITE = 0,   // set when a margin, residual or weight is NaN/Inf
     FLAG_TIMEOUT = 1,     // set when a grid barrier exceeded its spin limit
-    FLAG_BAR_COUNT = 32,  // grid barrier: generation word, then the top arrival
-                          // counter, then eight group counters, each on its
-                          // own 128-byte line (words 32 .. 351)
-    FLAG_BAR_GEN = 32,
-    FLAG_BAR_TOP = 64,
-    FLAG_BAR_GROUP = 96,  // + 32 * group
-    FLAG_WORDS = 352
+    FLAG_BAR_COUNT = 32,  // first barrier word (everything from here is cleared
+                          // before a fused launch)
+    // a barrier's words from its base: generation, top arrival counter, then
+    // eight group counters, each on its own 128-byte line
+    BAR_GEN = 0,
+    BAR_TOP = 32,
+    BAR_GROUP = 64,       // + 32 * group
+    BAR_WORDS = 320,
+    FLAG_BAR_MAIN = 32,   // the grid barrier
+    FLAG_BAR_SUB = 352,   // a barrier among a subset of the workgroups
+    FLAG_SLICES = 672,    // update slices finished in this launch (own line)
+    FLAG_WORDS = 704
 };
 
 // Entry points without a workspace pass flags == nullptr and report nothing.
@@ -207,17 +212,17 @@ __device__ __forceinline__ void raise_flag(unsigned* flags, int which) {
 // The wait is bounded: after `spin_limit` polls the timeout flag is raised
 // and every workgroup leaves the barrier (and then the kernel) at once, so a
 // launch can never wait forever. Returns false when the kernel must stop.
-__device__ __forceinline__ bool grid_barrier(unsigned* flags, unsigned member, unsigned nblocks,
-                                             unsigned long long spin_limit) {
+__device__ __forceinline__ bool barrier_at(unsigned* flags, int base, unsigned member,
+                                           unsigned nblocks, unsigned long long spin_limit) {
     __shared__ int s_stop;
     __syncthreads();
     if (threadIdx.x == 0) {
         const unsigned ng = nblocks < 8u ? nblocks : 8u;
         const unsigned g = member % ng;
         const unsigned in_group = (nblocks - g + ng - 1) / ng;
-        unsigned* gen = flags + FLAG_BAR_GEN;
-        unsigned* top = flags + FLAG_BAR_TOP;
-        unsigned* cnt = flags + FLAG_BAR_GROUP + 32 * g;
+        unsigned* gen = flags + base + BAR_GEN;
+        unsigned* top = flags + base + BAR_TOP;
+        unsigned* cnt = flags + base + BAR_GROUP + 32 * g;
         const unsigned g0 = atomic_load_relaxed(gen);
         int stop = 0;
         bool advanced = false;
@@ -254,6 +259,40 @@ __device__ __forceinline__ bool grid_barrier(unsigned* flags, unsigned member, u
     }
     __syncthreads();
     return s_stop == 0;
+}
+
+// Bounded wait (thread 0 for the workgroup) until the counter at word `w`
+// reaches `want`, then an acquire: the counted workgroups' writes are
+// visible to the whole workgroup. Returns false on timeout.
+__device__ __forceinline__ bool wait_count(unsigned* flags, int w, unsigned want,
+                                           unsigned long long spin_limit) {
+    __shared__ int s_ok;
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        unsigned long long spins = 0;
+        while (atomic_load_relaxed(flags + w) < want) {
+            if (++spins > spin_limit) {
+                raise_flag(flags, FLAG_TIMEOUT);
+                ok = 0;
+                break;
+            }
+            if ((spins & 255ull) == 0 && atomic_load_relaxed(flags + FLAG_TIMEOUT)) {
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        fence_acquire_agent();
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+// The grid barrier: every workgroup of the launch (or of one problem's group).
+__device__ __forceinline__ bool grid_barrier(unsigned* flags, unsigned member, unsigned nblocks,
+                                             unsigned long long spin_limit) {
+    return barrier_at(flags, FLAG_BAR_MAIN, member, nblocks, spin_limit);
 }
 
 }  // namespace casgd

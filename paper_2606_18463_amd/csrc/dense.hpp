@@ -51,6 +51,8 @@ struct Dense {
     float* sI[3];           // their row scales (1 when X has none)
     float* x_hist;          // snapshots or nullptr
     int64_t* t_hist;        // snapshot clocks or nullptr
+    int64_t* ptrace;        // phase clock (8 words per outer iteration) or nullptr
+    int64_t ptrace_outer;   // outer iterations traced
     int64_t snap_every;
     // fused-launch schedule
     uint64_t h0;            // first outer iteration
@@ -431,14 +433,14 @@ __device__ __forceinline__ void update_margin_slice(const Dense& P, int slice, c
     constexpr int VEC = Store<DT>::kVec;
     constexpr int KW = slice_width<DT>();
     constexpr int RPW = kWave / kLPR;
-    constexpr int U = 8;
+    constexpr int U = 16;   // rows in flight per lane: 1024 rows per workgroup pass
     constexpr int STRIDE = NW * RPW;
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
     const int sub = lane % kLPR, rg = lane / kLPR;
     const int64_t col0 = (int64_t)slice * KW;
     const int64_t kl = col0 + sub * VEC;
-    const V16 zero = {{0u, 0u, 0u, 0u}};
+    const int sbpad = P.ts * kTile;   // rows of the gathered block (zero-padded)
 
     if (do_update) {
         const int slot = slot_of(h);
@@ -450,18 +452,19 @@ __device__ __forceinline__ void update_margin_slice(const Dense& P, int slice, c
         for (int t0 = w * RPW + rg; t0 < P.sb; t0 += STRIDE * U) {
             V16 v[U];
             float ct[U];
+            // Unconditional loads (a conditional load becomes a branch whose
+            // join waits for it): rows past sb are clamped into the zero rows
+            // that pad the block to whole tiles (or to its last row) and get
+            // the weight 0.
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int t = t0 + u * STRIDE;
-                const bool ok = t < P.sb;
-                if (ok) {
-                    const uint4 q = *reinterpret_cast<const uint4*>(Y + (int64_t)t * P.ldy);
-                    v[u].w[0] = q.x; v[u].w[1] = q.y; v[u].w[2] = q.z; v[u].w[3] = q.w;
-                    ct[u] = c[t] * sI[t];
-                } else {
-                    v[u] = zero;
-                    ct[u] = 0.f;
-                }
+                const int tc = t < sbpad ? t : sbpad - 1;
+                const int tw = t < P.sb ? t : P.sb - 1;
+                const uint4 q = *reinterpret_cast<const uint4*>(Y + (int64_t)tc * P.ldy);
+                v[u].w[0] = q.x; v[u].w[1] = q.y; v[u].w[2] = q.z; v[u].w[3] = q.w;
+                const float cw = c[tw] * sI[tw];
+                ct[u] = t < P.sb ? cw : 0.f;
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
@@ -509,12 +512,9 @@ __device__ __forceinline__ void update_margin_slice(const Dense& P, int slice, c
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int t = t0 + u * STRIDE;
-                if (t < P.sb) {
-                    const uint4 q = *reinterpret_cast<const uint4*>(Y + (int64_t)t * P.ldy);
-                    v[u].w[0] = q.x; v[u].w[1] = q.y; v[u].w[2] = q.z; v[u].w[3] = q.w;
-                } else {
-                    v[u] = zero;
-                }
+                const int tc = t < sbpad ? t : sbpad - 1;
+                const uint4 q = *reinterpret_cast<const uint4*>(Y + (int64_t)tc * P.ldy);
+                v[u].w[0] = q.x; v[u].w[1] = q.y; v[u].w[2] = q.z; v[u].w[3] = q.w;
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {

@@ -9,6 +9,13 @@
 
 namespace casgd {
 
+// Phase clock: thread 0 of the workgroup records the device clock in word
+// `k` of outer iteration hh when tracing is on.
+__device__ __forceinline__ void phase_mark(const Dense& P, int64_t hh, int k) {
+    if (P.ptrace && threadIdx.x == 0 && hh < P.ptrace_outer)
+        P.ptrace[hh * 8 + k] = (int64_t)wall_clock64();
+}
+
 // Margins of outer iteration h from the slices' partial sums: eight lanes per
 // row, lane e adding slices e, e+8, ... in order, then a fixed tree over the
 // eight lanes; times the row scale. Threads gtid of nthreads (multiples of 8).
@@ -81,7 +88,7 @@ __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigne
     const int gw = wg * kNW + wave, ngw = nb * kNW;
 
     // Prologue: gather the rows of h0 and h0+1; then the Gram of h0 and the
-    // margins of h0 from the incoming x (variant 3: reduced to P.r).
+    // margins of h0 from the incoming x.
     gather_rows<DT>(P, h0, gw, ngw);
     if (H > 1) gather_rows<DT>(P, h0 + 1, gw, ngw);
     if (!grid_barrier(P.flags, wg, nb, spin)) return;
@@ -89,11 +96,6 @@ __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigne
     for (int sl = wg; sl < P.nslices; sl += nb)
         update_margin_slice<DT, kNW>(P, sl, nullptr, 0, false, h0, true, P.rp[0], red, xs, -1);
     if (!grid_barrier(P.flags, wg, nb, spin)) return;
-    if (MULTI && P.variant == 3) {
-        reduce_margins(P, P.rp[0], h0, P.r, wg * kNT + (int)threadIdx.x, nb * kNT);
-        if (!grid_barrier(P.flags, wg, nb, spin)) return;
-    }
-
     for (int64_t hh = 0; hh < H; ++hh) {
         const uint64_t h = h0 + (uint64_t)hh;
         const int cur = (int)(hh & 1), nxt = cur ^ 1;
@@ -102,25 +104,73 @@ __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigne
         const bool snap = P.snap_every > 0 && ((hh + 1) % P.snap_every) == 0;
         const int64_t snap_row = snap ? (hh + 1) / P.snap_every - 1 : -1;
         if (MULTI && P.variant == 3) {
-            // recurrence of h on workgroups 0 .. nrec-1 (chain + helpers);
-            // Gram of h+1 and rows of h+2 on the others
+            // Phase A: workgroups 0 .. nrec-1 reduce the margins of h, meet
+            // at their own barrier and run the recurrence of h (chain +
+            // helpers); the others build the Gram of h+1.
             const int nrec = 1 + rec_helpers(P.b, P.s);
+            if (wg == 0) phase_mark(P, hh, 0);
+            if (hh == 0) {
+                // margins of h0 (from the prologue): reduced by the recurrence
+                // workgroups themselves
+                if (wg < nrec) {
+                    reduce_margins(P, pick2(P.rp, cur), h, P.r, wg * kNT + (int)threadIdx.x,
+                                   nrec * kNT);
+                    if (!barrier_at(P.flags, FLAG_BAR_SUB, wg, nrec, spin)) return;
+                }
+            }
             if (wg < nrec) {
                 rec_multi_rank<ACC>(P, pick2(P.G, cur), P.r, pick3(P.yI, slot_of(h)), P.c, spin, lds,
                                     wg);
-            } else {
-                if (has_gram && more)
-                    gram_phase<DT>(P, pick2(P.G, nxt), h + 1, base + nrec, base + nb, lds);
-                if (more2) gather_rows<DT>(P, h + 2, gw - nrec * kNW, ngw - nrec * kNW);
+                if (wg == 0) phase_mark(P, hh, 1);
+            } else if (has_gram && more) {
+                gram_phase<DT>(P, pick2(P.G, nxt), h + 1, base + nrec, base + nb, lds);
             }
+            if (wg == nrec) phase_mark(P, hh, 2);
+            if (wg == nb - 1) phase_mark(P, hh, 6);
             if (!grid_barrier(P.flags, wg, nb, spin)) return;
+            if (wg == 0) phase_mark(P, hh, 3);
+            // Phase B: update of h fused with the margins of h+1 on the
+            // column slices; workgroups without a slice gather the rows of h+2.
+            // With more workgroups than slices, the ones without a slice gather
+            // the rows of h+2, then wait until every slice has published its
+            // partial margins (a counter that grows by nslices per outer
+            // iteration) and reduce them, so the next recurrence finds them.
+            // Otherwise everybody updates, gathers, and the reduction waits
+            // for the next phase.
+            const bool split = nb > P.nslices;
             for (int sl = wg; sl < P.nslices; sl += nb)
                 update_margin_slice<DT, kNW>(P, sl, P.c, h, true, h + 1, more, pick2(P.rp, nxt), red,
                                              xs, snap_row);
+            if (wg == 0) phase_mark(P, hh, 4);
+            if (split && wg < P.nslices && more) {
+                __syncthreads();
+                if (threadIdx.x == 0)
+                    __hip_atomic_fetch_add(P.flags + FLAG_SLICES, 1u, __ATOMIC_RELEASE,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (more2) {
+                if (split) {
+                    if (wg >= P.nslices)
+                        gather_rows<DT>(P, h + 2, gw - P.nslices * kNW, ngw - P.nslices * kNW);
+                } else {
+                    gather_rows<DT>(P, h + 2, gw, ngw);
+                }
+            }
+            if (split && wg >= P.nslices && more) {
+                const unsigned want = (unsigned)P.nslices * (unsigned)(hh + 1);
+                if (!wait_count(P.flags, FLAG_SLICES, want, spin)) return;
+                reduce_margins(P, pick2(P.rp, nxt), h + 1, P.r,
+                               (wg - P.nslices) * kNT + (int)threadIdx.x, (nb - P.nslices) * kNT);
+            }
+            if (wg == nb - 1) phase_mark(P, hh, 7);
             if (!grid_barrier(P.flags, wg, nb, spin)) return;
-            if (more) {
-                reduce_margins(P, pick2(P.rp, nxt), h + 1, P.r, wg * kNT + (int)threadIdx.x, nb * kNT);
-                if (!grid_barrier(P.flags, wg, nb, spin)) return;
+            if (wg == 0) phase_mark(P, hh, 5);
+            if (!split && more) {
+                if (wg < nrec) {
+                    reduce_margins(P, pick2(P.rp, nxt), h + 1, P.r, wg * kNT + (int)threadIdx.x,
+                                   nrec * kNT);
+                    if (!barrier_at(P.flags, FLAG_BAR_SUB, wg, nrec, spin)) return;
+                }
             }
         } else if (P.variant == 1) {
             if (wg < P.nslices) {
