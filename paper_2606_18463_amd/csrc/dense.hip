@@ -1,15 +1,13 @@
 // Kernels and launchers of the dense s-step SGD path.
 //
-// Two execution forms share the device functions of dense.hpp:
-//  * one launch per phase (gram, recurrence, update+next margin), stream
-//    ordered; kernel boundaries are the synchronisation points;
-//  * one persistent cooperative launch for a whole fit, with grid barriers.
-//    Variant 1 ("redundant"): every workgroup that owns update slices runs
-//    the recurrence itself, so an outer iteration needs one barrier; this
-//    suits small s*b (plain SGD at s = 1 is this variant). Variant 2
-//    ("single"): workgroup 0 runs the recurrence while all others compute
-//    the next outer iteration's Gram tiles (which do not depend on x), then
-//    everyone applies the update; two barriers per outer iteration.
+// Two execution forms share the device functions of dense.hpp,
+// recurrence.hpp and fit.hpp:
+//  * one launch per phase, stream ordered (kernel boundaries are the
+//    synchronisation points): gather of the next block with the margin
+//    reduction, Gram, recurrence (multi-workgroup for b = 16, 32, 64, 128),
+//    update fused with the next margins;
+//  * one persistent cooperative launch for a whole fit (fit.hpp), in three
+//    variants (see fit_body), and the batched launch of many problems.
 #include <algorithm>
 #include <cstring>
 
@@ -30,26 +28,9 @@ template <int DT>
 __global__ __launch_bounds__(kNT) void k_gather(Dense P, uint64_t h, int do_gather,
                                                 const float* rp, uint64_t hr, float* r_out) {
     if (do_gather) gather_rows<DT>(P, h, blockIdx.x * kNW + (threadIdx.x >> 6), gridDim.x * kNW);
-    if (rp) {
-        // margins of outer iteration hr: eight lanes per row, lane e adding
-        // the slices e, e+8, ... in order, then a fixed tree over the eight
-        // lanes; times the row scale
-        const float* sI = pick3(P.sI, slot_of(hr));
-        const int e = threadIdx.x & 7;
-        const int rows_per_pass = gridDim.x * (blockDim.x >> 3);
-        for (int t0 = blockIdx.x * (blockDim.x >> 3); t0 < P.sb; t0 += rows_per_pass) {
-            const int t = t0 + (threadIdx.x >> 3);
-            float a = 0.f;
-            if (t < P.sb) {
-#pragma unroll 8
-                for (int sl = e; sl < P.nslices; sl += 8) a += rp[(int64_t)sl * P.sb + t];
-            }
-            a += shfl_xor(a, 1);
-            a += shfl_xor(a, 2);
-            a += shfl_xor(a, 4);
-            if (t < P.sb && e == 0) r_out[t] = a * sI[t];
-        }
-    }
+    if (rp)
+        reduce_margins(P, rp, hr, r_out, (int)(blockIdx.x * blockDim.x + threadIdx.x),
+                       (int)(gridDim.x * blockDim.x));
 }
 
 template <int DT>

@@ -38,10 +38,10 @@ struct Dense {
     int nslices;            // column slices of the update / margin passes
     int64_t ldy;            // row stride (elements) of the gathered rows: n rounded up to 128
     unsigned* flags;        // FLAG_* words
-    unsigned* tile_cnt;     // split-K arrival counters, one per tile
+    unsigned* tile_cnt;     // split-K arrival counters, one per Gram unit (2 * ntiles words)
     float* G[2];            // sb x ldg, row-major, strict block-lower part used
     int64_t ldg;            // row stride of G (sb plus a pad that spreads rows over channels)
-    float* Gpart;           // ntiles * ksplit * 4096 split-K partial tiles
+    float* Gpart;           // split-K partial units (ntiles * ksplit * 4096 floats)
     float* rp[2];           // nslices x sb partial margins
     float* c;               // sb corrected residual weights
     float* r;               // sb reduced margins (row scales applied)

@@ -63,6 +63,17 @@ __host__ __device__ inline size_t fit_lds_bytes(int sb, int s, int acc_bytes, in
 
 // One problem's whole fit on the workgroups wg = 0 .. nb-1 of its group (the
 // grid, or one group of a batched launch), with the group's own barrier.
+// Per outer iteration h:
+//  * variant 3 (MULTI): phase A, workgroups 0 .. R run the multi-workgroup
+//    recurrence of h while the others build the Gram of h+1; barrier;
+//    phase B, the column-slice workgroups apply the update of h fused with
+//    the partial margins of h+1, the others gather the rows of h+2 and then
+//    reduce those margins once every slice has counted in; barrier.
+//  * variant 1: every update workgroup runs the single-workgroup recurrence
+//    itself, updates its slices, then everybody builds the next Gram and
+//    gathers; one barrier (small s*b, plain SGD).
+//  * variant 2: workgroup 0 runs the single-workgroup recurrence while the
+//    others build the next Gram and gather; barrier; update; barrier.
 template <int DT, typename ACC, bool MULTI>
 __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigned long long spin,
                                          unsigned char* lds) {
