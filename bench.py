@@ -289,7 +289,12 @@ def c4_bench(cg, steps: int, warmup: int):
         eta = 2.0 ** k
         xl = torch.zeros(p.n, L, device="cuda")
         cg.casgd_fit_path(X, y, xl, lams, eta, b, s, SEED, 0, quarter, ws=ws)
-        cg.casgd_check(ws)
+        try:
+            cg.casgd_check(ws)
+        except cg.CasgdError as err:   # diverged: larger steps will too
+            log(f"[c4] eta={eta:g}: {err}")
+            cg.casgd_reset(ws)
+            break
         loss = float(cg.casgd_logloss(Xt, yt, xl.t().contiguous()).min())
         log(f"[c4] eta={eta:g}: best-lane test loss {loss:.6f}")
         if math.isfinite(loss) and (best is None or loss < best[0]):

@@ -81,8 +81,8 @@ enum { CASGD_DENSE = 0, CASGD_CSR = 1 };
  * DENSE: `values` (device) holds m rows of `ld` elements of `dtype`, row i at
  *   values + i*ld; ld >= n, ld*elementsize a multiple of 16 bytes and the base
  *   16-byte aligned. Columns n..ld-1 are never read.
- * CSR: `row_ptr` (device, int64, m+1), `col_idx` (device, int32, nnz, sorted
- *   within each row, < n) and `values` (device, FP32, nnz); dtype must be
+ * CSR: `row_ptr` (device, int64, m+1), `col_idx` (device, int32, nnz, strictly
+ *   increasing within each row, < n) and `values` (device, FP32, nnz); dtype must be
  *   CASGD_F32; ld is ignored.
  * `row_scale` (device, FP32, m) or NULL: the stored row i represents
  *   row_scale[i] * values[i,:]. Required for CASGD_FP8E4M3, optional otherwise.

@@ -85,10 +85,16 @@ __global__ __launch_bounds__(kNT) void k_sparse_fit(Sparse S, uint64_t h0, int64
         const bool more = hh + 1 < H, more2 = hh + 2 < H;
         const bool snap = S.snap_every > 0 && ((hh + 1) % S.snap_every) == 0;
         const int64_t snap_row = snap ? (hh + 1) / S.snap_every - 1 : -1;
+        auto mark = [&](int k) {
+            if (S.ptrace && threadIdx.x == 0 && hh < S.ptrace_outer)
+                S.ptrace[hh * 8 + k] = (int64_t)wall_clock64();
+        };
+        if (wg == 0) mark(0);
         if (wg < R) {
             const int l0 = wg * NL;
             sparse_recurrence<ACC, kNT>(S, spick2(S.G, (int)(h & 1)), h, l0, min(NL, S.L - l0), dl,
                                         pw, tpr);
+            if (wg == 0) mark(1);
         } else {
             const int w0 = (wg - R) * kNW + wave, nw = (nb - R) * kNW;
             const int t0 = (wg - R) * kNT + threadIdx.x, nt = (nb - R) * kNT;
@@ -97,14 +103,21 @@ __global__ __launch_bounds__(kNT) void k_sparse_fit(Sparse S, uint64_t h0, int64
                 sparse_bucket(S, h + 1, t0, nt);
             }
             if (more2) sparse_gather(S, h + 2, w0, nw, hrow);
+            if (wg == R) mark(2);
         }
         if (!grid_barrier(S.flags, wg, nb, spin)) return;
-        sparse_update(S, h, gw, ngw, gtid, nthr, snap_row);
+        if (wg == 0) mark(3);
+        // the wave's scratch for the tail update: its head-row buffer
+        sparse_update(S, h, gw, ngw, gtid, nthr, snap_row, reinterpret_cast<int2*>(hrow));
+        if (wg == 0) mark(4);
         if (more) sparse_gram_tail(S, h + 1, spick2(S.G, (int)((h + 1) & 1)), gtid, nthr);
+        if (wg == 0) mark(5);
         if (!grid_barrier(S.flags, wg, nb, spin)) return;
+        if (wg == 0) mark(6);
         if (more) sparse_margins(S, h + 1, gw, ngw);
         sparse_clear_buckets(S, h, gtid, nthr);
         if (!grid_barrier(S.flags, wg, nb, spin)) return;
+        if (wg == 0) mark(7);
         if (snap && wg == 0 && threadIdx.x == 0 && S.t_hist)
             S.t_hist[snap_row + 1] = (int64_t)wall_clock64();
     }
@@ -378,6 +391,10 @@ casgd_status sparse_fit(const casgd_matrix* X, const float* y, float* x_lanes,
         S.snap_every = opts->snapshot_every;
         S.x_hist = opts->x_history;
         S.t_hist = opts->t_history;
+    }
+    if (opts && opts->phase_trace && opts->phase_trace_outer > 0) {
+        S.ptrace = opts->phase_trace;
+        S.ptrace_outer = opts->phase_trace_outer;
     }
     // Gram view over the head panel.
     Dense& Gv = S.gram;

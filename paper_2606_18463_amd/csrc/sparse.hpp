@@ -57,6 +57,8 @@ struct Sparse {
     float* x_hist;
     int64_t* t_hist;
     int64_t snap_every;
+    int64_t* ptrace;        // phase clock (8 words per outer iteration) or nullptr
+    int64_t ptrace_outer;
     Dense gram;             // view for the head-panel Gram (MFMA tiles)
 };
 
@@ -64,6 +66,14 @@ template <typename T>
 __device__ __forceinline__ T spick3(const T (&a)[3], int k) {
     return k == 0 ? a[0] : (k == 1 ? a[1] : a[2]);
 }
+// Orders this wave's LDS accesses (a wave-scope barrier for scratch that only
+// the wave uses).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
 template <typename T>
 __device__ __forceinline__ T spick2(const T (&a)[2], int k) {
     return k == 0 ? a[0] : a[1];
@@ -220,11 +230,12 @@ __device__ __forceinline__ void sparse_margins(const Sparse& S, uint64_t h, int 
 // Update of outer h for all lanes: x <- beta^s x + alpha * Y^T c.
 //  * head columns: one wave per (16 head columns, 16 lanes) tile computes
 //    Yh^T c (H x rows times rows x lanes) with FP32 MFMA 16x16x4;
-//  * tail columns present in the block: the owner is the bucket entry with
-//    the smallest t; it sums the bucket in increasing t;
+//  * tail columns present in the block: one wave per column sums its bucket
+//    in increasing t for every lane (see below);
 //  * all other columns: x <- beta^s x.
 __device__ __forceinline__ void sparse_update(const Sparse& S, uint64_t h, int wave_id, int nwaves,
-                                              int gtid, int nthreads, int64_t snap_row) {
+                                              int gtid, int nthreads, int64_t snap_row,
+                                              int2* sorted) {
     const int lane = threadIdx.x & 63;
     const int slot = slot_of(h);
     const float* Yh = spick3(S.Yh, slot);
@@ -268,42 +279,66 @@ __device__ __forceinline__ void sparse_update(const Sparse& S, uint64_t h, int w
             }
         }
     }
-    // tail columns of the block
+    // Tail columns of the block. The owner of a column is its bucket entry
+    // with the smallest t; each wave scans 64 entries at a time, and for each
+    // owner among them the whole wave handles the column: lane q ranks bucket
+    // entry q by t (the t of a column's entries are distinct) and stores it
+    // at its rank in the wave's LDS scratch, then lane l (one per lambda lane)
+    // adds the entries in increasing t, four loads in flight at a time.
     const int64_t total = (int64_t)S.sb * S.maxlen;
-    for (int64_t e = gtid; e < total; e += nthreads) {
-        const int t = (int)(e / S.maxlen), kk = (int)(e - (int64_t)t * S.maxlen);
-        if (kk >= tlen[t]) continue;
-        const int col = tcol[e];
-        const int cnt = min((int)bcnt[col], kBucketCap);
-        const int2* be = bent + (int64_t)col * kBucketCap;
-        int tmin = t;
-        for (int q = 0; q < cnt; ++q) tmin = min(tmin, be[q].x);
-        if (tmin != t) continue;
-        for (int lc = 0; lc < L; lc += 8) {
-            float g[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) g[u] = 0.f;
-            int last = -1;
-            for (int done = 0; done < cnt; ++done) {   // entries in increasing t
-                int nxt = 0x7fffffff;
-                float v = 0.f;
-                for (int q = 0; q < cnt; ++q) {
-                    const int2 en = be[q];
-                    if (en.x > last && en.x < nxt) { nxt = en.x; v = __int_as_float(en.y); }
-                }
-                last = nxt;
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    if (lc + u < L) g[u] = fmaf(v, S.c[(int64_t)nxt * L + lc + u], g[u]);
+    for (int64_t e0 = (int64_t)wave_id * 64; e0 < total; e0 += (int64_t)nwaves * 64) {
+        const int64_t e = e0 + lane;
+        bool own = false;
+        int col = 0;
+        if (e < total) {
+            const int t = (int)(e / S.maxlen), kk = (int)(e - (int64_t)t * S.maxlen);
+            if (kk < tlen[t]) {
+                col = tcol[e];
+                const int cnt = min((int)bcnt[col], kBucketCap);
+                const int2* be = bent + (int64_t)col * kBucketCap;
+                int tmin = t;
+                for (int q = 0; q < cnt; ++q) tmin = min(tmin, be[q].x);
+                own = tmin == t;
             }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int l = lc + u;
-                if (l >= L) break;
-                const float xn = S.lbs[l] * S.x[(int64_t)col * L + l] + alpha * g[u];
-                S.x[(int64_t)col * L + l] = xn;
+        }
+        unsigned long long mask = __ballot(own);
+        while (mask) {
+            const int src = __ffsll((unsigned long long)mask) - 1;
+            mask &= mask - 1;
+            const int ccol = __shfl(col, src, kWave);
+            const int cnt = min((int)bcnt[ccol], kBucketCap);
+            const int2 en = lane < cnt ? bent[(int64_t)ccol * kBucketCap + lane]
+                                       : make_int2(0x7fffffff, 0);
+            int rank = 0;
+            for (int q = 0; q < cnt; ++q) {
+                const int tq = __shfl(en.x, q, kWave);
+                rank += (tq < en.x || (tq == en.x && q < lane)) ? 1 : 0;
+            }
+            wave_lds_sync();
+            if (lane < cnt) sorted[rank] = en;
+            wave_lds_sync();
+            const int l = lane;
+            if (l < L) {
+                float g = 0.f;
+                int p = 0;
+                for (; p + 4 <= cnt; p += 4) {
+                    const int2 e0v = sorted[p], e1v = sorted[p + 1], e2v = sorted[p + 2],
+                               e3v = sorted[p + 3];
+                    const float c0 = S.c[(int64_t)e0v.x * L + l], c1 = S.c[(int64_t)e1v.x * L + l],
+                                c2 = S.c[(int64_t)e2v.x * L + l], c3 = S.c[(int64_t)e3v.x * L + l];
+                    g = fmaf(__int_as_float(e0v.y), c0, g);
+                    g = fmaf(__int_as_float(e1v.y), c1, g);
+                    g = fmaf(__int_as_float(e2v.y), c2, g);
+                    g = fmaf(__int_as_float(e3v.y), c3, g);
+                }
+                for (; p < cnt; ++p) {
+                    const int2 ev = sorted[p];
+                    g = fmaf(__int_as_float(ev.y), S.c[(int64_t)ev.x * L + l], g);
+                }
+                const float xn = S.lbs[l] * S.x[(int64_t)ccol * L + l] + alpha * g;
+                S.x[(int64_t)ccol * L + l] = xn;
                 if (!isfinite(xn)) raise_flag(S.flags, FLAG_NONFINITE);
-                if (snap_row >= 0) S.x_hist[(snap_row * S.n + col) * L + l] = xn;
+                if (snap_row >= 0) S.x_hist[(snap_row * S.n + ccol) * L + l] = xn;
             }
         }
     }
