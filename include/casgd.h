@@ -128,7 +128,7 @@ typedef struct {
      *   compute the next outer iteration's Gram (two barriers);
      * fused_variant 3 = the multi-workgroup recurrence (chain + helpers, as
      *   in exec_mode 2) runs while the other workgroups compute the next
-     *   Gram; three barriers (b = 16, 32, 64, 128; not in casgd_fit_batch);
+     *   Gram; two grid barriers (b = 16, 32, 64, 128; not in casgd_fit_batch);
      * grid_blocks = number of workgroups of the fused launch (capped at the
      *   number that can be resident). */
     int32_t fused_variant;
@@ -145,6 +145,10 @@ typedef struct {
      * untouched. */
     int64_t *phase_trace;
     int64_t phase_trace_outer;
+    /* CSR lambda path (casgd_fit_path): workgroups that share the
+     * recurrence of one group of four lanes, splitting the rows of every
+     * block; a power of two dividing b (0 = automatic). */
+    int32_t rec_split;
 } casgd_opts;
 
 const char *casgd_status_string(casgd_status st);

@@ -116,13 +116,14 @@ def csr_matrix(row_ptr, col_idx, values, n: int) -> MatrixRef:
 
 def opts(recur_prec: int = 0, exec_mode: int = 0, snapshot_every: int = 0, x_history=None,
          t_history=None, spin_limit: int = 0, fused_variant: int = 0, grid_blocks: int = 0,
-         phase_trace=None):
+         phase_trace=None, rec_split: int = 0):
     """casgd_opts; phase_trace: device int64 tensor of 8 words per traced outer iteration."""
     o = _lib.Opts(recur_prec=recur_prec, exec_mode=exec_mode, snapshot_every=snapshot_every,
                   x_history=_ptr(x_history), t_history=_ptr(t_history), spin_limit=spin_limit,
                   fused_variant=fused_variant, grid_blocks=grid_blocks,
                   phase_trace=_ptr(phase_trace),
-                  phase_trace_outer=0 if phase_trace is None else phase_trace.numel() // 8)
+                  phase_trace_outer=0 if phase_trace is None else phase_trace.numel() // 8,
+                  rec_split=rec_split)
     o._keep = (x_history, t_history, phase_trace)
     return o
 

@@ -44,8 +44,9 @@ __host__ __device__ inline size_t sparse_lds_bytes(int sb, int s, int acc_bytes,
     return off < kGramLds ? kGramLds : off;
 }
 
-// Per outer iteration h, with R recurrence workgroups (kLanesPerRecWG lanes
-// each) and the remaining workgroups as workers:
+// Per outer iteration h, with R recurrence workgroups (K per group of
+// kLanesPerRecWG lanes, splitting the rows of each block) and the remaining
+// workgroups as workers:
 //   P1  recurrence(h)            | Gram head(h+1), gather(h+2), buckets(h+1)
 //   --  barrier
 //   P2  update(h), Gram tail(h+1)
@@ -54,7 +55,7 @@ __host__ __device__ inline size_t sparse_lds_bytes(int sb, int s, int acc_bytes,
 //   --  barrier
 template <typename ACC>
 __global__ __launch_bounds__(kNT) void k_sparse_fit(Sparse S, uint64_t h0, int64_t H,
-                                                    unsigned long long spin, int tpr, int R) {
+                                                    unsigned long long spin, int K, int R) {
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr int NL = kLanesPerRecWG;
     ACC* dl = reinterpret_cast<ACC*>(lds);
@@ -91,9 +92,9 @@ __global__ __launch_bounds__(kNT) void k_sparse_fit(Sparse S, uint64_t h0, int64
         };
         if (wg == 0) mark(0);
         if (wg < R) {
-            const int l0 = wg * NL;
-            sparse_recurrence<ACC, kNT>(S, spick2(S.G, (int)(h & 1)), h, l0, min(NL, S.L - l0), dl,
-                                        pw, tpr);
+            const int l0 = (wg / K) * NL;
+            sparse_recurrence<ACC, kNT>(S, spick2(S.G, (int)(h & 1)), h, l0, min(NL, S.L - l0),
+                                        wg % K, K, dl, pw, spin);
             if (wg == 0) mark(1);
         } else {
             const int w0 = (wg - R) * kNW + wave, nw = (nb - R) * kNW;
@@ -107,6 +108,7 @@ __global__ __launch_bounds__(kNT) void k_sparse_fit(Sparse S, uint64_t h0, int64
         }
         if (!grid_barrier(S.flags, wg, nb, spin)) return;
         if (wg == 0) mark(3);
+        if (wg < R) sparse_pub_clear(S, (wg / K) * NL, min(NL, S.L - (wg / K) * NL), wg % K, K);
         // the wave's scratch for the tail update: its head-row buffer
         sparse_update(S, h, gw, ngw, gtid, nthr, snap_row, reinterpret_cast<int2*>(hrow));
         if (wg == 0) mark(4);
@@ -130,7 +132,7 @@ namespace {
 struct SparseLayout {
     int sb, sbpad, maxlen, L;
     DenseLayout gl;  // Gram tiles over the head panel (n = kHeadMax, FP32)
-    size_t off_flags, off_tilecnt, off_G0, off_G1, off_Gpart, off_r, off_c, off_lbeta, off_lbs,
+    size_t off_flags, off_tilecnt, off_G0, off_G1, off_Gpart, off_r, off_c, off_pub, off_lbeta, off_lbs,
         off_headid, off_headcol, off_colcnt, off_Yh[3], off_tcol[3], off_tval[3], off_tlen[3],
         off_yI[3], off_bcnt[2], off_bent[2], total;
 };
@@ -153,6 +155,7 @@ void sparse_layout(int64_t n, int b, int s, int L, int maxlen, SparseLayout* S) 
     take(S->off_Gpart, S->gl.ksplit > 1 ? (size_t)S->gl.ntiles * S->gl.ksplit * 4096 * 4 : 0);
     take(S->off_r, sb * L * 4);
     take(S->off_c, sb * L * 4);
+    take(S->off_pub, sb * L * 16);
     take(S->off_lbeta, (size_t)kMaxLanes * 8);
     take(S->off_lbs, (size_t)kMaxLanes * 4);
     take(S->off_headid, (size_t)n * 4);
@@ -383,6 +386,7 @@ casgd_status sparse_fit(const casgd_matrix* X, const float* y, float* x_lanes,
     S.G[1] = at<float>(ws, SL.off_G1);
     S.r = at<float>(ws, SL.off_r);
     S.c = at<float>(ws, SL.off_c);
+    S.pub = at<unsigned long long>(ws, SL.off_pub);
     if (opts && opts->snapshot_every > 0) {
         if (!opts->x_history) {
             set_error("snapshot_every > 0 needs x_history");
@@ -457,19 +461,36 @@ casgd_status sparse_fit(const casgd_matrix* X, const float* y, float* x_lanes,
     int per_cu = 0;
     CASGD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kNT, lds));
     const int maxg = per_cu * device_cus();
-    int R = (L + kLanesPerRecWG - 1) / kLanesPerRecWG;
+    const int groups = (L + kLanesPerRecWG - 1) / kLanesPerRecWG;
     int grid = (opts && opts->grid_blocks > 0) ? opts->grid_blocks : device_cus();
     grid = std::min(grid, maxg);
+    // Workgroups per lane group: a power of two dividing b; automatically 16
+    // rows per workgroup (fewer workgroups if they would take more than half
+    // of the grid), so the choice does not depend on the number of lanes
+    // unless the grid is small.
+    int K = 1;
+    if (opts && opts->rec_split > 0) {
+        K = opts->rec_split;
+        if ((K & (K - 1)) != 0 || b % K != 0) {
+            set_error("rec_split must be a power of two dividing b");
+            return CASGD_EINVAL;
+        }
+    } else {
+        while (b % (2 * K) == 0 && b / (2 * K) >= 16 && groups * 2 * K <= grid / 2) K *= 2;
+    }
+    int R = groups * K;
     if (grid <= R) {
         set_error("not enough resident workgroups (%d) for %d lanes", maxg, L);
         return CASGD_EUNSUPPORTED;
     }
     unsigned long long spin =
         (opts && opts->spin_limit > 0) ? (unsigned long long)opts->spin_limit : (1ull << 24);
-    int tpr = recurrence_tpr(kNT, b);
+    if (K > 1 && (rc = run_zero(reinterpret_cast<unsigned*>(S.pub), (int64_t)S.sb * L * 4, st)) !=
+                     CASGD_OK)
+        return rc;
     uint64_t h0 = outer_begin;
     int64_t Hn = n_outer;
-    void* args[] = {&S, &h0, &Hn, &spin, &tpr, &R};
+    void* args[] = {&S, &h0, &Hn, &spin, &K, &R};
     CASGD_HIP(hipLaunchCooperativeKernel(kern, dim3(grid), dim3(kNT), args, (unsigned)lds, st));
     return CASGD_OK;
 }

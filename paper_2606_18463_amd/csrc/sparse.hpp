@@ -13,7 +13,7 @@
 // and G; only margins, residuals, c and x are per lane (x is n x L).
 #pragma once
 
-#include "dense.hpp"
+#include "recurrence.hpp"
 
 namespace casgd {
 
@@ -57,6 +57,7 @@ struct Sparse {
     float* x_hist;
     int64_t* t_hist;
     int64_t snap_every;
+    unsigned long long* pub;  // delta exchange of the recurrence: 2 words per (row, lane)
     int64_t* ptrace;        // phase clock (8 words per outer iteration) or nullptr
     int64_t ptrace_outer;
     Dense gram;             // view for the head-panel Gram (MFMA tiles)
@@ -240,7 +241,6 @@ __device__ __forceinline__ void sparse_update(const Sparse& S, uint64_t h, int w
     const int slot = slot_of(h);
     const float* Yh = spick3(S.Yh, slot);
     const int32_t* tcol = spick3(S.tcol, slot);
-    const float* tval = spick3(S.tval, slot);
     const int32_t* tlen = spick3(S.tlen, slot);
     const unsigned* bcnt = spick2(S.bcnt, (int)(h & 1));
     const int2* bent = spick2(S.bent, (int)(h & 1));
@@ -367,64 +367,69 @@ __device__ __forceinline__ void sparse_clear_buckets(const Sparse& S, uint64_t h
     }
 }
 
-// Residual corrections for lanes [l0, l0 + nl), nl <= kLanesPerRecWG, by one
-// workgroup (b must be a multiple of 4): every 16-byte piece of the G row
-// prefix is loaded once and applied to all lanes of the group.
+// Residual corrections for lanes [l0, l0 + nl), nl <= kLanesPerRecWG, by the
+// K workgroups of one lane group; workgroup k of the group owns rows
+// [k b/K, (k+1) b/K) of every row block. In step j each computes z_j and
+// delta_j of its own rows (every 16-byte piece of a G row prefix is loaded
+// once and applied to all lanes of the group), publishes the deltas as tagged
+// words and collects those of the other rows before step j + 1. The owner of
+// a word clears it after the grid barrier that follows the recurrence, so
+// every outer iteration starts from cleared words.
 // LDS: dl (sb x kLanesPerRecWG ACC), pw (kLanesPerRecWG x (s+1) ACC).
 template <typename ACC, int NT>
 __device__ __forceinline__ void sparse_recurrence(const Sparse& S, const float* G, uint64_t h,
-                                                  int l0, int nl, ACC* dl, ACC* pw, int TPR) {
+                                                  int l0, int nl, int k, int K, ACC* dl, ACC* pw,
+                                                  unsigned long long spin) {
     constexpr int NL = kLanesPerRecWG;
     const int tid = threadIdx.x;
     const int b = S.b, s = S.s, sb = S.sb, L = S.L;
+    const int RB = b / K, q_lo = k * RB;
+    // threads per row: a power of two, at most one wave
+    int TPR = 1;
+    while (TPR < 64 && 2 * TPR * RB <= NT) TPR *= 2;
+    const int RPP = NT / TPR;
+    const int sub = tid % TPR;
     if (tid < NL) {
         ACC p = 1;
         const ACC be = tid < nl ? (ACC)S.lbeta[l0 + tid] : (ACC)1;
-        for (int k = 0; k <= s; ++k) { pw[tid * (s + 1) + k] = p; p *= be; }
+        for (int q = 0; q <= s; ++q) { pw[tid * (s + 1) + q] = p; p *= be; }
     }
     __syncthreads();
     const ACC alpha = (ACC)S.alpha_d;
-    const int RPP = NT / TPR;
-    const int sub = tid % TPR;
     const float* yI = spick3(S.yI, slot_of(h));
     for (int j = 0; j < s; ++j) {
-        for (int q0 = 0; q0 < b; q0 += RPP) {
+        const int nv = (j * b) >> 2;   // 16-byte pieces of the row prefix
+        for (int q0 = 0; q0 < RB; q0 += RPP) {
             const int q = q0 + tid / TPR;
-            const bool active = q < b;
-            const int t = j * b + q;
+            const bool active = q < RB;
+            const int t = j * b + q_lo + min(q, RB - 1);
             ACC acc[NL];
 #pragma unroll
             for (int l = 0; l < NL; ++l) acc[l] = 0;
-            if (active) {
-                const float4* g4 = reinterpret_cast<const float4*>(G + (int64_t)t * sb);
-                const int nv = (j * b) >> 2;
-                for (int base = sub; base < nv; base += kRB * TPR) {
-                    float4 g[kRB];
+            const float4* g4 = reinterpret_cast<const float4*>(G + (int64_t)t * sb);
+            for (int base = sub; base < nv; base += kRB * TPR) {
+                float4 g[kRB];
 #pragma unroll
-                    for (int k = 0; k < kRB; ++k) {
-                        const int v = base + k * TPR;
-                        g[k] = v < nv ? g4[v] : make_float4(0.f, 0.f, 0.f, 0.f);
-                    }
+                for (int u = 0; u < kRB; ++u) g[u] = g4[min(base + u * TPR, nv - 1)];
 #pragma unroll
-                    for (int k = 0; k < kRB; ++k) {
-                        const int v = base + k * TPR;
-                        if (v < nv) {
-                            const int u = 4 * v;
-                            const int i = u / b;
-                            const ACC* d = dl + u * NL;
+                for (int u = 0; u < kRB; ++u) {
+                    const int v = base + u * TPR;
+                    if (v < nv) {
+                        const int e = 4 * v;
+                        const int i = e / b;
+                        const ACC* d = dl + e * NL;
 #pragma unroll
-                            for (int l = 0; l < NL; ++l) {
-                                const ACC part = (ACC)g[k].x * d[l] + (ACC)g[k].y * d[NL + l] +
-                                                 (ACC)g[k].z * d[2 * NL + l] +
-                                                 (ACC)g[k].w * d[3 * NL + l];
-                                acc[l] += pw[l * (s + 1) + (j - 1 - i)] * part;
-                            }
+                        for (int l = 0; l < NL; ++l) {
+                            const ACC part = (ACC)g[u].x * d[l] + (ACC)g[u].y * d[NL + l] +
+                                             (ACC)g[u].z * d[2 * NL + l] +
+                                             (ACC)g[u].w * d[3 * NL + l];
+                            acc[l] += pw[l * (s + 1) + (j - 1 - i)] * part;
                         }
                     }
                 }
-#pragma unroll
-                for (int l = 0; l < NL; ++l) acc[l] = group_sum_rt(acc[l], TPR);
             }
+#pragma unroll
+            for (int l = 0; l < NL; ++l) acc[l] = group_sum_rt(acc[l], TPR);
             if (active && sub == 0) {
                 const ACC yv = (ACC)yI[t];
 #pragma unroll
@@ -436,13 +441,39 @@ __device__ __forceinline__ void sparse_recurrence(const Sparse& S, const float* 
                         if (!isfinite(z)) raise_flag(S.flags, FLAG_NONFINITE);
                         dl[t * NL + l] = d;
                         S.c[(int64_t)t * L + l0 + l] = (float)(pw[l * (s + 1) + (s - 1 - j)] * d);
+                        if (K > 1 && j + 1 < s) pub_put(S.pub + 2 * ((int64_t)t * L + l0 + l), d);
                     } else {
                         dl[t * NL + l] = 0;
                     }
                 }
             }
         }
+        if (K > 1 && j + 1 < s) {
+            // deltas of the rows the other workgroups of the group own
+            for (int w = tid; w < b * NL; w += NT) {
+                const int q = w / NL, l = w - q * NL;
+                if (q >= q_lo && q < q_lo + RB) continue;
+                const int t = j * b + q;
+                ACC d = 0;
+                if (l < nl) pub_wait(S.pub + 2 * ((int64_t)t * L + l0 + l), d, S.flags, spin);
+                dl[t * NL + l] = d;
+            }
+        }
         __syncthreads();
+    }
+}
+
+// Clears the exchange words of the rows a recurrence workgroup owns (after
+// the grid barrier that ends the recurrence).
+__device__ __forceinline__ void sparse_pub_clear(const Sparse& S, int l0, int nl, int k, int K) {
+    if (K <= 1) return;
+    const int b = S.b, RB = b / K, n = (S.s - 1) * RB * nl;
+    for (int w = threadIdx.x; w < n; w += blockDim.x) {
+        const int l = w % nl, rq = w / nl, j = rq / RB, q = rq - j * RB;
+        const int64_t t = (int64_t)j * b + k * RB + q;
+        unsigned long long* p = S.pub + 2 * (t * S.L + l0 + l);
+        __hip_atomic_store(p, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(p + 1, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

@@ -69,6 +69,42 @@ def test_lanes_match_oracle_and_solo_runs(cg, small):
         assert torch.equal(solo[:, 0], xl[:, l]), l
 
 
+@pytest.mark.parametrize("K", [1, 2, 8, 32])
+def test_recurrence_split_matches_oracle(cg, small, K):
+    """The lane-group recurrence split over K workgroups (rows of each block
+    divided among them, deltas exchanged between steps): every split matches
+    the oracle, and the unsplit form to rounding."""
+    p = small
+    X = _csr(cg, p)
+    y = _dev(p.y)
+    lams = [0.0, 1e-4, 3e-3, 1e-2, 5e-2]
+    L, b, s, H = len(lams), 32, 8, 30
+    ws = cg.casgd_sparse_prepare(X, b, s, L)
+    out = {}
+    for k in sorted({1, K}):
+        xl = torch.zeros(p.n, L, device="cuda")
+        cg.casgd_fit_path(X, y, xl, lams, 1.5, b, s, 9, 0, H, opts=cg.opts(rec_split=k), ws=ws)
+        cg.casgd_check(ws)
+        out[k] = xl.cpu().numpy().astype(np.float64)
+    for l in (0, 4):
+        xo = R.casgd_csr(p.row_ptr, p.col_idx, p.values, p.n, p.y, np.zeros(p.n), 1.5, lams[l],
+                         b, s, 9, 0, H)
+        assert np.linalg.norm(out[K][:, l] - xo) / np.linalg.norm(xo) < 1e-4, l
+    assert np.linalg.norm(out[K] - out[1]) / np.linalg.norm(out[1]) < 1e-6
+
+
+def test_recurrence_split_rejects_bad_values(cg, small):
+    p = small
+    X = _csr(cg, p)
+    y = _dev(p.y)
+    ws = cg.casgd_sparse_prepare(X, 32, 8, 2)
+    xl = torch.zeros(p.n, 2, device="cuda")
+    for k in (3, 64):
+        with pytest.raises(cg.CasgdError):
+            cg.casgd_fit_path(X, y, xl, [0.0, 1e-3], 1.5, 32, 8, 9, 0, 1,
+                              opts=cg.opts(rec_split=k), ws=ws)
+
+
 def test_sparse_equals_dense_on_densified(cg, small):
     p = small
     D = p.to_dense()
