@@ -64,6 +64,8 @@ __global__ __launch_bounds__(kNT) void k_sparse_fit(Sparse S, uint64_t h0, int64
     off = (off + 15) & ~(size_t)15;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float* hrow = reinterpret_cast<float*>(lds + off) + (size_t)wave * S.Hp;
+    // outside the recurrence the lane deltas' space holds one row of G per wave
+    float* rowbuf = reinterpret_cast<float*>(lds) + (size_t)wave * S.sb;
 
     const int nb = gridDim.x, wg = blockIdx.x;
     const int gw = wg * kNW + wave, ngw = nb * kNW;
@@ -77,8 +79,8 @@ __global__ __launch_bounds__(kNT) void k_sparse_fit(Sparse S, uint64_t h0, int64
     sparse_bucket(S, h0, gtid, nthr);
     gram_phase<DT_F32>(S.gram, spick2(S.G, (int)(h0 & 1)), h0, 0, nb, lds);
     if (!grid_barrier(S.flags, wg, nb, spin)) return;
-    sparse_gram_tail(S, h0, spick2(S.G, (int)(h0 & 1)), gtid, nthr);
-    sparse_margins(S, h0, gw, ngw);
+    sparse_gram_tail(S, h0, spick2(S.G, (int)(h0 & 1)), gw, ngw, rowbuf);
+    sparse_margins(S, h0, reinterpret_cast<float*>(lds));
     if (!grid_barrier(S.flags, wg, nb, spin)) return;
 
     for (int64_t hh = 0; hh < H; ++hh) {
@@ -110,13 +112,14 @@ __global__ __launch_bounds__(kNT) void k_sparse_fit(Sparse S, uint64_t h0, int64
         if (wg == 0) mark(3);
         if (wg < R) sparse_pub_clear(S, (wg / K) * NL, min(NL, S.L - (wg / K) * NL), wg % K, K);
         // the wave's scratch for the tail update: its head-row buffer
-        sparse_update(S, h, gw, ngw, gtid, nthr, snap_row, reinterpret_cast<int2*>(hrow));
+        sparse_update(S, h, gw, ngw, gtid, nthr, snap_row, reinterpret_cast<int2*>(hrow),
+                      reinterpret_cast<float*>(lds));
         if (wg == 0) mark(4);
-        if (more) sparse_gram_tail(S, h + 1, spick2(S.G, (int)((h + 1) & 1)), gtid, nthr);
+        if (more) sparse_gram_tail(S, h + 1, spick2(S.G, (int)((h + 1) & 1)), gw, ngw, rowbuf);
         if (wg == 0) mark(5);
         if (!grid_barrier(S.flags, wg, nb, spin)) return;
         if (wg == 0) mark(6);
-        if (more) sparse_margins(S, h + 1, gw, ngw);
+        if (more) sparse_margins(S, h + 1, reinterpret_cast<float*>(lds));
         sparse_clear_buckets(S, h, gtid, nthr);
         if (!grid_barrier(S.flags, wg, nb, spin)) return;
         if (wg == 0) mark(7);
@@ -464,10 +467,9 @@ casgd_status sparse_fit(const casgd_matrix* X, const float* y, float* x_lanes,
     const int groups = (L + kLanesPerRecWG - 1) / kLanesPerRecWG;
     int grid = (opts && opts->grid_blocks > 0) ? opts->grid_blocks : device_cus();
     grid = std::min(grid, maxg);
-    // Workgroups per lane group: a power of two dividing b; automatically 16
+    // Workgroups per lane group: a power of two dividing b; automatically 8
     // rows per workgroup (fewer workgroups if they would take more than half
-    // of the grid), so the choice does not depend on the number of lanes
-    // unless the grid is small.
+    // of the grid).
     int K = 1;
     if (opts && opts->rec_split > 0) {
         K = opts->rec_split;
@@ -476,7 +478,7 @@ casgd_status sparse_fit(const casgd_matrix* X, const float* y, float* x_lanes,
             return CASGD_EINVAL;
         }
     } else {
-        while (b % (2 * K) == 0 && b / (2 * K) >= 16 && groups * 2 * K <= grid / 2) K *= 2;
+        while (b % (2 * K) == 0 && b / (2 * K) >= 8 && groups * 2 * K <= grid / 2) K *= 2;
     }
     int R = groups * K;
     if (grid <= R) {

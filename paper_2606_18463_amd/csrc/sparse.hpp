@@ -6,9 +6,10 @@
 //   * a dense FP32 head panel Yh (rows x Hp), whose Gram is computed with the
 //     same MFMA tile routine as the dense path, and
 //   * per-row tail lists (column, value).
-// Tail columns are appended to per-column buckets; the owner of G row t then
-// adds v_t v_u for every bucket entry u of an earlier block, visiting its own
-// columns in order, so every G entry is accumulated in a fixed order.
+// Tail columns are appended to per-column buckets; the wave that owns G row t
+// then adds v_t v_u for every bucket entry u of an earlier block, visiting
+// the row's columns in order, so every G entry is accumulated in a fixed
+// order.
 // L lanes (regularisation strengths) share the samples, the gathered rows
 // and G; only margins, residuals, c and x are per lane (x is n x L).
 #pragma once
@@ -149,42 +150,64 @@ __device__ __forceinline__ void sparse_bucket(const Sparse& S, uint64_t h, int g
     }
 }
 
-// Tail part of the Gram of outer h: the owner thread of row t adds
-// v_t v_u into G[t][u] for each of its tail columns (in column order) and each
-// bucket entry u of an earlier block. Must run after the head-panel Gram.
-__device__ __forceinline__ void sparse_gram_tail(const Sparse& S, uint64_t h, float* G, int gtid,
-                                                 int nthreads) {
+// Tail part of the Gram of outer h: one wave per row t of blocks 1.. . It
+// visits the row's tail columns in column order; for each, the lanes take the
+// column's bucket entries u of earlier blocks (distinct rows, so no two lanes
+// touch the same u) and add v_t v_u into a row buffer in LDS (`rowbuf`, sb
+// floats of this wave). The buffer is then added to G row t. Every G entry is
+// thus accumulated in a fixed order. Must run after the head-panel Gram.
+__device__ __forceinline__ void sparse_gram_tail(const Sparse& S, uint64_t h, float* G,
+                                                 int wave_id, int nwaves, float* rowbuf) {
+    const int lane = threadIdx.x & 63;
     const int slot = slot_of(h);
     const int32_t* tcol = spick3(S.tcol, slot);
     const float* tval = spick3(S.tval, slot);
     const int32_t* tlen = spick3(S.tlen, slot);
     const unsigned* bcnt = spick2(S.bcnt, (int)(h & 1));
     const int2* bent = spick2(S.bent, (int)(h & 1));
-    for (int t = gtid; t < S.sb; t += nthreads) {
-        const int bt = t / S.b;
-        if (bt == 0) continue;
+    const int ql = min(lane, kBucketCap - 1);
+    for (int t = S.b + wave_id; t < S.sb; t += nwaves) {
         const int nt = tlen[t];
-        for (int k = 0; k < nt; ++k) {
-            const int col = tcol[(int64_t)t * S.maxlen + k];
-            const float vt = tval[(int64_t)t * S.maxlen + k];
+        if (nt == 0) continue;
+        const int pre = (t / S.b) * S.b;   // columns of earlier blocks
+        for (int u = lane; u < pre; u += 64) rowbuf[u] = 0.f;
+        wave_lds_sync();
+        for (int k0 = 0; k0 < nt; k0 += 64) {
+            const int kn = min(64, nt - k0);
+            const int64_t ek = (int64_t)t * S.maxlen + k0 + min(lane, kn - 1);
+            const int col = tcol[ek];
+            const float vt = tval[ek];
             const int cnt = min((int)bcnt[col], kBucketCap);
-            const int2* be = bent + (int64_t)col * kBucketCap;
-            for (int q = 0; q < cnt; ++q) {
-                const int2 e = be[q];
-                if (e.x / S.b < bt) G[(int64_t)t * S.sb + e.x] += vt * __int_as_float(e.y);
+            // entry of the next column, loaded one step ahead
+            int2 nxt = bent[(int64_t)__shfl(col, 0, kWave) * kBucketCap + ql];
+            for (int k = 0; k < kn; ++k) {
+                const int2 e = nxt;
+                const float v = __shfl(vt, k, kWave);
+                const int c = __shfl(cnt, k, kWave);
+                const int kk = min(k + 1, kn - 1);
+                nxt = bent[(int64_t)__shfl(col, kk, kWave) * kBucketCap + ql];
+                if (lane < c && e.x < pre) rowbuf[e.x] += v * __int_as_float(e.y);
+                wave_lds_sync();
             }
         }
+        float* grow = G + (int64_t)t * S.sb;
+        for (int u = lane; u < pre; u += 64) {
+            const float v = rowbuf[u];
+            if (v != 0.f) grow[u] += v;
+        }
+        wave_lds_sync();
     }
 }
 
-// Margins of outer h for all lanes. One wave per (16 rows, 16 lanes) tile:
-// the head part R = Yh Xh (rows x H times H x lanes) with FP32 MFMA
-// 16x16x4, then each lane adds the tail entries of its four outputs' rows.
-// Output layout of the 16x16 MFMA: lane q, register v hold row 4*(q/16)+v,
-// column q%16 of the tile.
-__device__ __forceinline__ void sparse_margins(const Sparse& S, uint64_t h, int wave_id,
-                                               int nwaves) {
-    const int lane = threadIdx.x & 63;
+// Margins of outer h for all lanes. One workgroup per (16 rows, 16 lanes)
+// tile: the head part R = Yh Xh (rows x H times H x lanes) with FP32 MFMA
+// 16x16x4, wave w taking the 16-column chunks w, w + 4, ... (four chunks of
+// loads in flight), the partial tiles added in wave order through LDS (`red`,
+// 4 KB); then thread (i, j) of the tile adds the tail entries of row i in
+// column order, eight loads in flight. Output layout of the 16x16 MFMA: lane
+// q, register v hold row 4*(q/16)+v, column q%16 of the tile.
+__device__ __forceinline__ void sparse_margins(const Sparse& S, uint64_t h, float* red) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int slot = slot_of(h);
     const float* Yh = spick3(S.Yh, slot);
     const int32_t* tcol = spick3(S.tcol, slot);
@@ -193,50 +216,89 @@ __device__ __forceinline__ void sparse_margins(const Sparse& S, uint64_t h, int 
     const int L = S.L;
     const int rt = (S.sb + 15) / 16, lt = (L + 15) / 16;
     const int li = lane & 15, lg = lane >> 4;
-    for (int item = wave_id; item < rt * lt; item += nwaves) {
+    const int nhc = (S.H + 15) / 16;
+    __syncthreads();   // `red` may still be in use by the previous phase
+    for (int item = blockIdx.x; item < rt * lt; item += gridDim.x) {
         const int t0 = (item / lt) * 16, l0 = (item % lt) * 16;
         v4f acc[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) acc[k] = v4f{0.f, 0.f, 0.f, 0.f};
-        const int jl = l0 + li;
-        const bool lok = jl < L;
-        // A[i][k] = Yh[t0+i][hc0+k] (lane: i = li, k = lg); B[k][j] = x[head_col[hc0+k]][l0+j]
-        const float* arow = Yh + (int64_t)(t0 + li) * S.Hp;
-        for (int hc0 = 0; hc0 < S.H; hc0 += 16) {
+        {
+            const int jl = l0 + li;
+            const bool lok = jl < L;
+            const int jlc = min(jl, L - 1);
+            // A[i][k] = Yh[t0+i][hc0+k] (lane: i = li, k = lg); B[k][j] = x[head_col[hc0+k]][l0+j]
+            const float* arow = Yh + (int64_t)(t0 + li) * S.Hp;   // padded rows are zero
+            for (int c0 = wave; c0 < nhc; c0 += 4 * kNW) {
+                float a[4][4], bv[4][4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int hc = hc0 + 4 * k + lg;
-                const float a = arow[hc];
-                const float bv = (hc < S.H && lok) ? S.x[(int64_t)S.head_col[hc] * L + jl] : 0.f;
-                acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc[k], 0, 0, 0);
+                for (int u = 0; u < 4; ++u) {
+                    const int cc = min(c0 + u * kNW, nhc - 1);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int hc = cc * 16 + 4 * k + lg;
+                        a[u][k] = arow[hc];
+                        bv[u][k] = S.x[(int64_t)S.head_col[min(hc, S.H - 1)] * L + jlc];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (c0 + u * kNW < nhc) {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const int hc = (c0 + u * kNW) * 16 + 4 * k + lg;
+                            const float w = (hc < S.H && lok) ? bv[u][k] : 0.f;
+                            acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][k], w, acc[k], 0, 0, 0);
+                        }
+                    }
+                }
             }
         }
-        v4f d = acc[0] + acc[1] + acc[2] + acc[3];
-        if (lok) {
+        const v4f g = acc[0] + acc[1] + acc[2] + acc[3];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int t = t0 + 4 * lg + v;
-                if (t >= S.sb) continue;
-                float r = d[v];
+        for (int v = 0; v < 4; ++v) red[(wave * 64 + lane) * 4 + v] = g[v];
+        __syncthreads();
+        {
+            const int i = threadIdx.x >> 4, j = threadIdx.x & 15;   // 256 threads: 16 x 16
+            const int t = t0 + i, jl = l0 + j;
+            if (t < S.sb && jl < L) {
+                const int q = 16 * (i >> 2) + j, v = i & 3;
+                float r = red[q * 4 + v];
+#pragma unroll
+                for (int w = 1; w < kNW; ++w) r += red[(w * 64 + q) * 4 + v];
                 const int nt = tlen[t];
-                for (int k = 0; k < nt; ++k)
-                    r = fmaf(tval[(int64_t)t * S.maxlen + k],
-                             S.x[(int64_t)tcol[(int64_t)t * S.maxlen + k] * L + jl], r);
+                const int64_t base = (int64_t)t * S.maxlen;
+                for (int k0 = 0; k0 < nt; k0 += 8) {
+                    int cl[8];
+                    float vl[8], xv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int kk = min(k0 + u, nt - 1);
+                        cl[u] = tcol[base + kk];
+                        vl[u] = tval[base + kk];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) xv[u] = S.x[(int64_t)cl[u] * L + jl];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (k0 + u < nt) r = fmaf(vl[u], xv[u], r);
+                }
                 S.r[(int64_t)t * L + jl] = r;
             }
         }
+        __syncthreads();
     }
 }
 
 // Update of outer h for all lanes: x <- beta^s x + alpha * Y^T c.
-//  * head columns: one wave per (16 head columns, 16 lanes) tile computes
-//    Yh^T c (H x rows times rows x lanes) with FP32 MFMA 16x16x4;
+//  * head columns: one workgroup per (16 head columns, 16 lanes) tile
+//    computes Yh^T c (H x rows times rows x lanes) with FP32 MFMA 16x16x4;
 //  * tail columns present in the block: one wave per column sums its bucket
 //    in increasing t for every lane (see below);
 //  * all other columns: x <- beta^s x.
 __device__ __forceinline__ void sparse_update(const Sparse& S, uint64_t h, int wave_id, int nwaves,
                                               int gtid, int nthreads, int64_t snap_row,
-                                              int2* sorted) {
+                                              int2* sorted, float* red) {
     const int lane = threadIdx.x & 63;
     const int slot = slot_of(h);
     const float* Yh = spick3(S.Yh, slot);
@@ -247,37 +309,66 @@ __device__ __forceinline__ void sparse_update(const Sparse& S, uint64_t h, int w
     const int L = S.L;
     const float alpha = (float)S.alpha_d;
     const int li = lane & 15, lg = lane >> 4;
-    // head columns: D[i][j] = sum_t Yh[t][hc0+i] c[t][l0+j]
+    // Head columns: D[i][j] = sum_t Yh[t][hc0+i] c[t][l0+j]. One workgroup
+    // per (16 head columns, 16 lanes) tile; wave w takes the 16-row chunks
+    // w, w + 4, ... (four chunks of loads in flight) and the four partial
+    // tiles are added in wave order through LDS (`red`, 4 KB).
     const int ht = (S.H + 15) / 16, lt = (L + 15) / 16;
-    for (int item = wave_id; item < ht * lt; item += nwaves) {
+    const int wave = wave_id % kNW;
+    const int nch = (S.sb + 15) / 16;
+    for (int item = blockIdx.x; item < ht * lt; item += gridDim.x) {
         const int hc0 = (item / lt) * 16, l0 = (item % lt) * 16;
         const int jl = l0 + li;
         const bool lok = jl < L;
+        const int jlc = min(jl, L - 1);
         v4f acc[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) acc[k] = v4f{0.f, 0.f, 0.f, 0.f};
-        for (int t0 = 0; t0 < S.sb; t0 += 16) {
+        for (int c0 = wave; c0 < nch; c0 += 4 * kNW) {
+            float a[4][4], bv[4][4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int t = t0 + 4 * k + lg;
-                const float a = Yh[(int64_t)t * S.Hp + hc0 + li];  // padded rows are zero
-                const float bv = (t < S.sb && lok) ? S.c[(int64_t)t * L + jl] : 0.f;
-                acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc[k], 0, 0, 0);
+            for (int u = 0; u < 4; ++u) {
+                const int ch = min(c0 + u * kNW, nch - 1);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int t = ch * 16 + 4 * k + lg;   // < sbpad: padded rows are zero
+                    a[u][k] = Yh[(int64_t)t * S.Hp + hc0 + li];
+                    bv[u][k] = S.c[(int64_t)min(t, S.sb - 1) * L + jlc];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int ch = c0 + u * kNW;
+                if (ch < nch) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int t = ch * 16 + 4 * k + lg;
+                        const float w = (t < S.sb && lok) ? bv[u][k] : 0.f;
+                        acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][k], w, acc[k], 0, 0, 0);
+                    }
+                }
             }
         }
         const v4f g = acc[0] + acc[1] + acc[2] + acc[3];
-        if (lok) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[(wave * 64 + lane) * 4 + v] = g[v];
+        __syncthreads();
+        if (wave == 0 && lok) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
+                float d = red[lane * 4 + v];
+#pragma unroll
+                for (int w = 1; w < kNW; ++w) d += red[(w * 64 + lane) * 4 + v];
                 const int hc = hc0 + 4 * lg + v;
                 if (hc >= S.H) continue;
                 const int64_t k = S.head_col[hc];
-                const float xn = S.lbs[jl] * S.x[k * L + jl] + alpha * g[v];
+                const float xn = S.lbs[jl] * S.x[k * L + jl] + alpha * d;
                 S.x[k * L + jl] = xn;
                 if (!isfinite(xn)) raise_flag(S.flags, FLAG_NONFINITE);
                 if (snap_row >= 0) S.x_hist[(snap_row * S.n + k) * L + jl] = xn;
             }
         }
+        __syncthreads();
     }
     // Tail columns of the block. The owner of a column is its bucket entry
     // with the smallest t; each wave scans 64 entries at a time, and for each
@@ -342,7 +433,42 @@ __device__ __forceinline__ void sparse_update(const Sparse& S, uint64_t h, int w
             }
         }
     }
-    // untouched columns: decay only
+    // Untouched columns: decay only. With L a multiple of 4 and 16-byte
+    // aligned x (and history), four lanes at a time, four column pieces of
+    // loads in flight per thread.
+    const bool vec = (L & 3) == 0 && ((uintptr_t)S.x & 15) == 0 &&
+                     (snap_row < 0 || ((uintptr_t)S.x_hist & 15) == 0);
+    if (vec) {
+        const int LQ = L >> 2;
+        const int64_t nq = S.n * LQ;
+        float4* x4 = reinterpret_cast<float4*>(S.x);
+        const float4* lb4 = reinterpret_cast<const float4*>(S.lbs);
+        for (int64_t base = gtid; base < nq; base += 4 * (int64_t)nthreads) {
+            int hid[4];
+            unsigned bc[4];
+            float4 xv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t q = min(base + u * (int64_t)nthreads, nq - 1);
+                const int64_t k = q / LQ;
+                hid[u] = S.head_id[k];
+                bc[u] = bcnt[k];
+                xv[u] = x4[q];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t q = base + u * (int64_t)nthreads;
+                if (q < nq && hid[u] < 0 && bc[u] == 0u) {
+                    const float4 be = lb4[q % LQ];
+                    const float4 xn = make_float4(be.x * xv[u].x, be.y * xv[u].y, be.z * xv[u].z,
+                                                  be.w * xv[u].w);
+                    x4[q] = xn;
+                    if (snap_row >= 0) reinterpret_cast<float4*>(S.x_hist + snap_row * S.n * L)[q] = xn;
+                }
+            }
+        }
+        return;
+    }
     for (int64_t q = gtid; q < S.n * L; q += nthreads) {
         const int64_t k = q / L;
         const int l = (int)(q - k * L);
@@ -375,7 +501,7 @@ __device__ __forceinline__ void sparse_clear_buckets(const Sparse& S, uint64_t h
 // words and collects those of the other rows before step j + 1. The owner of
 // a word clears it after the grid barrier that follows the recurrence, so
 // every outer iteration starts from cleared words.
-// LDS: dl (sb x kLanesPerRecWG ACC), pw (kLanesPerRecWG x (s+1) ACC).
+// LDS: dl (kLanesPerRecWG x sb ACC, lane-major), pw (kLanesPerRecWG x (s+1) ACC).
 template <typename ACC, int NT>
 __device__ __forceinline__ void sparse_recurrence(const Sparse& S, const float* G, uint64_t h,
                                                   int l0, int nl, int k, int K, ACC* dl, ACC* pw,
@@ -397,6 +523,22 @@ __device__ __forceinline__ void sparse_recurrence(const Sparse& S, const float* 
     __syncthreads();
     const ACC alpha = (ACC)S.alpha_d;
     const float* yI = spick3(S.yI, slot_of(h));
+    // First batch of G pieces, residuals and labels of a step's first row
+    // pass, loaded one step ahead (while the deltas of the step before are
+    // exchanged).
+    float4 gp[kRB];
+    float rp[NL], yp;
+    auto load_first = [&](int jj) {
+        const int nvj = max((jj * b) >> 2, 1);
+        const int t = jj * b + q_lo + min(tid / TPR, RB - 1);
+        const float4* g4 = reinterpret_cast<const float4*>(G + (int64_t)t * sb);
+#pragma unroll
+        for (int u = 0; u < kRB; ++u) gp[u] = g4[min(sub + u * TPR, nvj - 1)];
+#pragma unroll
+        for (int l = 0; l < NL; ++l) rp[l] = S.r[(int64_t)t * L + l0 + min(l, nl - 1)];
+        yp = yI[t];
+    };
+    load_first(0);
     for (int j = 0; j < s; ++j) {
         const int nv = (j * b) >> 2;   // 16-byte pieces of the row prefix
         for (int q0 = 0; q0 < RB; q0 += RPP) {
@@ -406,23 +548,37 @@ __device__ __forceinline__ void sparse_recurrence(const Sparse& S, const float* 
             ACC acc[NL];
 #pragma unroll
             for (int l = 0; l < NL; ++l) acc[l] = 0;
+            float rr[NL], yv;
+            if (q0 == 0) {
+#pragma unroll
+                for (int l = 0; l < NL; ++l) rr[l] = rp[l];
+                yv = yp;
+            } else {
+#pragma unroll
+                for (int l = 0; l < NL; ++l) rr[l] = S.r[(int64_t)t * L + l0 + min(l, nl - 1)];
+                yv = yI[t];
+            }
             const float4* g4 = reinterpret_cast<const float4*>(G + (int64_t)t * sb);
             for (int base = sub; base < nv; base += kRB * TPR) {
                 float4 g[kRB];
+                if (q0 == 0 && base == sub) {
 #pragma unroll
-                for (int u = 0; u < kRB; ++u) g[u] = g4[min(base + u * TPR, nv - 1)];
+                    for (int u = 0; u < kRB; ++u) g[u] = gp[u];
+                } else {
+#pragma unroll
+                    for (int u = 0; u < kRB; ++u) g[u] = g4[min(base + u * TPR, nv - 1)];
+                }
 #pragma unroll
                 for (int u = 0; u < kRB; ++u) {
                     const int v = base + u * TPR;
                     if (v < nv) {
                         const int e = 4 * v;
                         const int i = e / b;
-                        const ACC* d = dl + e * NL;
 #pragma unroll
                         for (int l = 0; l < NL; ++l) {
-                            const ACC part = (ACC)g[u].x * d[l] + (ACC)g[u].y * d[NL + l] +
-                                             (ACC)g[u].z * d[2 * NL + l] +
-                                             (ACC)g[u].w * d[3 * NL + l];
+                            const ACC* d = dl + l * sb + e;   // lane-major: 4 consecutive rows
+                            const ACC part = (ACC)g[u].x * d[0] + (ACC)g[u].y * d[1] +
+                                             (ACC)g[u].z * d[2] + (ACC)g[u].w * d[3];
                             acc[l] += pw[l * (s + 1) + (j - 1 - i)] * part;
                         }
                     }
@@ -430,33 +586,66 @@ __device__ __forceinline__ void sparse_recurrence(const Sparse& S, const float* 
             }
 #pragma unroll
             for (int l = 0; l < NL; ++l) acc[l] = group_sum_rt(acc[l], TPR);
-            if (active && sub == 0) {
-                const ACC yv = (ACC)yI[t];
+            // every thread of the row group holds the sums; thread l % TPR
+            // finishes lane l
+            if (active) {
 #pragma unroll
                 for (int l = 0; l < NL; ++l) {
+                    if ((l & (TPR - 1)) != sub) continue;
+                    ACC d = 0;
                     if (l < nl) {
-                        const ACC r = (ACC)S.r[(int64_t)t * L + l0 + l];
-                        const ACC z = pw[l * (s + 1) + j] * r + alpha * acc[l];
-                        const ACC d = yv / ((ACC)1 + exp(yv * z));
+                        const ACC z = pw[l * (s + 1) + j] * (ACC)rr[l] + alpha * acc[l];
+                        d = (ACC)yv / ((ACC)1 + exp((ACC)yv * z));
                         if (!isfinite(z)) raise_flag(S.flags, FLAG_NONFINITE);
-                        dl[t * NL + l] = d;
                         S.c[(int64_t)t * L + l0 + l] = (float)(pw[l * (s + 1) + (s - 1 - j)] * d);
                         if (K > 1 && j + 1 < s) pub_put(S.pub + 2 * ((int64_t)t * L + l0 + l), d);
-                    } else {
-                        dl[t * NL + l] = 0;
                     }
+                    dl[l * sb + t] = d;
                 }
             }
         }
+        if (j + 1 < s) load_first(j + 1);
         if (K > 1 && j + 1 < s) {
-            // deltas of the rows the other workgroups of the group own
-            for (int w = tid; w < b * NL; w += NT) {
-                const int q = w / NL, l = w - q * NL;
-                if (q >= q_lo && q < q_lo + RB) continue;
-                const int t = j * b + q;
-                ACC d = 0;
-                if (l < nl) pub_wait(S.pub + 2 * ((int64_t)t * L + l0 + l), d, S.flags, spin);
-                dl[t * NL + l] = d;
+            // Deltas of the rows the other workgroups of the group own, four
+            // per thread at a time: all their words are read, then the ones
+            // still missing are read again.
+            constexpr int kP = 4;
+            for (int w0 = tid; w0 < b * NL; w0 += kP * NT) {
+                const unsigned long long* pp[kP];
+                ACC d[kP];
+                bool need[kP];
+#pragma unroll
+                for (int u = 0; u < kP; ++u) {
+                    const int w = w0 + u * NT;
+                    const int q = w / NL, l = w - q * NL;
+                    need[u] = w < b * NL && (q < q_lo || q >= q_lo + RB) && l < nl;
+                    pp[u] = S.pub + 2 * ((int64_t)(j * b + min(q, b - 1)) * L + l0 + min(l, nl - 1));
+                    d[u] = 0;
+                }
+                unsigned long long n = 0;
+                for (;;) {
+                    bool all = true;
+#pragma unroll
+                    for (int u = 0; u < kP; ++u)
+                        if (need[u]) {
+                            need[u] = !pub_get(pp[u], d[u]);
+                            all = all && !need[u];
+                        }
+                    if (all) break;
+                    if (++n > spin) {
+                        raise_flag(S.flags, FLAG_TIMEOUT);
+                        break;
+                    }
+                    if ((n & 63ull) == 0 && atomic_load_relaxed(S.flags + FLAG_TIMEOUT)) break;
+                    __builtin_amdgcn_s_sleep(1);
+                }
+#pragma unroll
+                for (int u = 0; u < kP; ++u) {
+                    const int w = w0 + u * NT;
+                    const int q = w / NL;
+                    if (w < b * NL && (q < q_lo || q >= q_lo + RB))
+                        dl[(w - q * NL) * sb + j * b + q] = d[u];
+                }
             }
         }
         __syncthreads();
