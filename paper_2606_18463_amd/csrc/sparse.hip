@@ -137,7 +137,7 @@ struct SparseLayout {
     DenseLayout gl;  // Gram tiles over the head panel (n = kHeadMax, FP32)
     size_t off_flags, off_tilecnt, off_G0, off_G1, off_Gpart, off_r, off_c, off_pub, off_lbeta, off_lbs,
         off_headid, off_headcol, off_colcnt, off_Yh[3], off_tcol[3], off_tval[3], off_tlen[3],
-        off_yI[3], off_bcnt[2], off_bent[2], total;
+        off_yI[3], off_bcnt[2], off_bent[2], off_tlist[2], off_tlcnt, total;
 };
 
 size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -174,7 +174,9 @@ void sparse_layout(int64_t n, int b, int s, int L, int maxlen, SparseLayout* S) 
     for (int k = 0; k < 2; ++k) {
         take(S->off_bcnt[k], (size_t)n * 4);
         take(S->off_bent[k], (size_t)n * kBucketCap * 8);
+        take(S->off_tlist[k], (size_t)n * 4);
     }
+    take(S->off_tlcnt, 2 * 4);
     S->total = off;
 }
 
@@ -384,12 +386,14 @@ casgd_status sparse_fit(const casgd_matrix* X, const float* y, float* x_lanes,
     for (int k = 0; k < 2; ++k) {
         S.bcnt[k] = at<unsigned>(ws, SL.off_bcnt[k]);
         S.bent[k] = at<int2>(ws, SL.off_bent[k]);
+        S.tlist[k] = at<int32_t>(ws, SL.off_tlist[k]);
     }
     S.G[0] = at<float>(ws, SL.off_G0);
     S.G[1] = at<float>(ws, SL.off_G1);
     S.r = at<float>(ws, SL.off_r);
     S.c = at<float>(ws, SL.off_c);
     S.pub = at<unsigned long long>(ws, SL.off_pub);
+    S.tlcnt = at<unsigned>(ws, SL.off_tlcnt);
     if (opts && opts->snapshot_every > 0) {
         if (!opts->x_history) {
             set_error("snapshot_every > 0 needs x_history");
@@ -445,6 +449,7 @@ casgd_status sparse_fit(const casgd_matrix* X, const float* y, float* x_lanes,
                        const_cast<double*>(S.lbeta), const_cast<float*>(S.lbs));
     CASGD_HIP(hipGetLastError());
     if ((rc = run_zero(Gv.tile_cnt, 2 * Gv.ntiles, st)) != CASGD_OK) return rc;
+    if ((rc = run_zero(S.tlcnt, 2, st)) != CASGD_OK) return rc;
     if ((rc = run_zero(S.flags + FLAG_BAR_COUNT, FLAG_WORDS - FLAG_BAR_COUNT, st)) != CASGD_OK)
         return rc;
 

@@ -52,6 +52,8 @@ struct Sparse {
     // per outer-iteration parity h % 2
     unsigned* bcnt[2];      // n
     int2* bent[2];          // n x kBucketCap of (t, value bits)
+    int32_t* tlist[2];      // n: the distinct tail columns of the block, in arrival order
+    unsigned* tlcnt;        // 2: their number, per parity
     float* G[2];
     float* r;               // sb x L
     float* c;               // sb x L
@@ -129,7 +131,8 @@ __device__ __forceinline__ void sparse_gather(const Sparse& S, uint64_t h, int w
     }
 }
 
-// Append every tail entry of outer h to its column's bucket (parity h % 2).
+// Append every tail entry of outer h to its column's bucket (parity h % 2);
+// the first entry of a column also appends the column to the tail list.
 __device__ __forceinline__ void sparse_bucket(const Sparse& S, uint64_t h, int gtid, int nthreads) {
     const int slot = slot_of(h);
     const int32_t* tcol = spick3(S.tcol, slot);
@@ -138,15 +141,39 @@ __device__ __forceinline__ void sparse_bucket(const Sparse& S, uint64_t h, int g
     unsigned* bcnt = spick2(S.bcnt, (int)(h & 1));
     int2* bent = spick2(S.bent, (int)(h & 1));
     const int64_t total = (int64_t)S.sb * S.maxlen;
-    for (int64_t e = gtid; e < total; e += nthreads) {
-        const int t = (int)(e / S.maxlen), k = (int)(e - (int64_t)t * S.maxlen);
-        if (k >= tlen[t]) continue;
-        const int col = tcol[e];
-        const unsigned pos = atomicAdd(bcnt + col, 1u);
-        if (pos < (unsigned)kBucketCap)
-            bent[(int64_t)col * kBucketCap + pos] = make_int2(t, __float_as_int(tval[e]));
-        else
-            raise_flag(S.flags, FLAG_OVERFLOW);
+    const int lane = threadIdx.x & 63;
+    // wave-uniform loop: new columns are appended to the tail list with one
+    // counter atomic per wave
+    for (int64_t e0 = gtid - lane; e0 < total; e0 += nthreads) {
+        const int64_t e = e0 + lane;
+        bool ok = e < total;
+        int t = 0, col = 0;
+        unsigned pos = 1u;
+        if (ok) {
+            t = (int)(e / S.maxlen);
+            const int k = (int)(e - (int64_t)t * S.maxlen);
+            ok = k < tlen[t];
+        }
+        if (ok) {
+            col = tcol[e];
+            pos = atomicAdd(bcnt + col, 1u);
+            if (pos < (unsigned)kBucketCap)
+                bent[(int64_t)col * kBucketCap + pos] = make_int2(t, __float_as_int(tval[e]));
+            else
+                raise_flag(S.flags, FLAG_OVERFLOW);
+        }
+        const unsigned long long first = __ballot(ok && pos == 0u);
+        if (first) {
+            unsigned base = 0;
+            if (lane == __ffsll((unsigned long long)first) - 1)
+                base = atomicAdd(S.tlcnt + (h & 1), (unsigned)__popcll(first));
+            base = __shfl(base, __ffsll((unsigned long long)first) - 1, kWave);
+            if (ok && pos == 0u) {
+                const unsigned ix = base + (unsigned)__popcll(first & ((1ull << lane) - 1ull));
+                if (ix < (unsigned)S.n) spick2(S.tlist, (int)(h & 1))[ix] = col;
+                else raise_flag(S.flags, FLAG_OVERFLOW);
+            }
+        }
     }
 }
 
@@ -302,8 +329,6 @@ __device__ __forceinline__ void sparse_update(const Sparse& S, uint64_t h, int w
     const int lane = threadIdx.x & 63;
     const int slot = slot_of(h);
     const float* Yh = spick3(S.Yh, slot);
-    const int32_t* tcol = spick3(S.tcol, slot);
-    const int32_t* tlen = spick3(S.tlen, slot);
     const unsigned* bcnt = spick2(S.bcnt, (int)(h & 1));
     const int2* bent = spick2(S.bent, (int)(h & 1));
     const int L = S.L;
@@ -370,67 +395,47 @@ __device__ __forceinline__ void sparse_update(const Sparse& S, uint64_t h, int w
         }
         __syncthreads();
     }
-    // Tail columns of the block. The owner of a column is its bucket entry
-    // with the smallest t; each wave scans 64 entries at a time, and for each
-    // owner among them the whole wave handles the column: lane q ranks bucket
-    // entry q by t (the t of a column's entries are distinct) and stores it
-    // at its rank in the wave's LDS scratch, then lane l (one per lambda lane)
-    // adds the entries in increasing t, four loads in flight at a time.
-    const int64_t total = (int64_t)S.sb * S.maxlen;
-    for (int64_t e0 = (int64_t)wave_id * 64; e0 < total; e0 += (int64_t)nwaves * 64) {
-        const int64_t e = e0 + lane;
-        bool own = false;
-        int col = 0;
-        if (e < total) {
-            const int t = (int)(e / S.maxlen), kk = (int)(e - (int64_t)t * S.maxlen);
-            if (kk < tlen[t]) {
-                col = tcol[e];
-                const int cnt = min((int)bcnt[col], kBucketCap);
-                const int2* be = bent + (int64_t)col * kBucketCap;
-                int tmin = t;
-                for (int q = 0; q < cnt; ++q) tmin = min(tmin, be[q].x);
-                own = tmin == t;
-            }
+    // Tail columns of the block, from the tail list: one wave per column. Lane
+    // q ranks bucket entry q by (t, bucket slot) and stores it at its rank in
+    // the wave's LDS scratch, then lane l (one per lambda lane) adds the
+    // entries in increasing t, four loads in flight at a time.
+    const int ncol = min((int)S.tlcnt[h & 1], (int)S.n);
+    const int32_t* tl = spick2(S.tlist, (int)(h & 1));
+    for (int ci = wave_id; ci < ncol; ci += nwaves) {
+        const int ccol = tl[ci];
+        const int cnt = min((int)bcnt[ccol], kBucketCap);
+        const int2 en = lane < cnt ? bent[(int64_t)ccol * kBucketCap + lane]
+                                   : make_int2(0x7fffffff, 0);
+        int rank = 0;
+        for (int q = 0; q < cnt; ++q) {
+            const int tq = __shfl(en.x, q, kWave);
+            rank += (tq < en.x || (tq == en.x && q < lane)) ? 1 : 0;
         }
-        unsigned long long mask = __ballot(own);
-        while (mask) {
-            const int src = __ffsll((unsigned long long)mask) - 1;
-            mask &= mask - 1;
-            const int ccol = __shfl(col, src, kWave);
-            const int cnt = min((int)bcnt[ccol], kBucketCap);
-            const int2 en = lane < cnt ? bent[(int64_t)ccol * kBucketCap + lane]
-                                       : make_int2(0x7fffffff, 0);
-            int rank = 0;
-            for (int q = 0; q < cnt; ++q) {
-                const int tq = __shfl(en.x, q, kWave);
-                rank += (tq < en.x || (tq == en.x && q < lane)) ? 1 : 0;
+        wave_lds_sync();
+        if (lane < cnt) sorted[rank] = en;
+        wave_lds_sync();
+        const int l = lane;
+        if (l < L) {
+            float g = 0.f;
+            int p = 0;
+            for (; p + 4 <= cnt; p += 4) {
+                const int2 e0v = sorted[p], e1v = sorted[p + 1], e2v = sorted[p + 2],
+                           e3v = sorted[p + 3];
+                const float c0 = S.c[(int64_t)e0v.x * L + l], c1 = S.c[(int64_t)e1v.x * L + l],
+                            c2 = S.c[(int64_t)e2v.x * L + l], c3 = S.c[(int64_t)e3v.x * L + l];
+                g = fmaf(__int_as_float(e0v.y), c0, g);
+                g = fmaf(__int_as_float(e1v.y), c1, g);
+                g = fmaf(__int_as_float(e2v.y), c2, g);
+                g = fmaf(__int_as_float(e3v.y), c3, g);
             }
-            wave_lds_sync();
-            if (lane < cnt) sorted[rank] = en;
-            wave_lds_sync();
-            const int l = lane;
-            if (l < L) {
-                float g = 0.f;
-                int p = 0;
-                for (; p + 4 <= cnt; p += 4) {
-                    const int2 e0v = sorted[p], e1v = sorted[p + 1], e2v = sorted[p + 2],
-                               e3v = sorted[p + 3];
-                    const float c0 = S.c[(int64_t)e0v.x * L + l], c1 = S.c[(int64_t)e1v.x * L + l],
-                                c2 = S.c[(int64_t)e2v.x * L + l], c3 = S.c[(int64_t)e3v.x * L + l];
-                    g = fmaf(__int_as_float(e0v.y), c0, g);
-                    g = fmaf(__int_as_float(e1v.y), c1, g);
-                    g = fmaf(__int_as_float(e2v.y), c2, g);
-                    g = fmaf(__int_as_float(e3v.y), c3, g);
-                }
-                for (; p < cnt; ++p) {
-                    const int2 ev = sorted[p];
-                    g = fmaf(__int_as_float(ev.y), S.c[(int64_t)ev.x * L + l], g);
-                }
-                const float xn = S.lbs[l] * S.x[(int64_t)ccol * L + l] + alpha * g;
-                S.x[(int64_t)ccol * L + l] = xn;
-                if (!isfinite(xn)) raise_flag(S.flags, FLAG_NONFINITE);
-                if (snap_row >= 0) S.x_hist[(snap_row * S.n + ccol) * L + l] = xn;
+            for (; p < cnt; ++p) {
+                const int2 ev = sorted[p];
+                g = fmaf(__int_as_float(ev.y), S.c[(int64_t)ev.x * L + l], g);
             }
+            const float xn = S.lbs[l] * S.x[(int64_t)ccol * L + l] + alpha * g;
+            S.x[(int64_t)ccol * L + l] = xn;
+            if (!isfinite(xn)) raise_flag(S.flags, FLAG_NONFINITE);
+            if (snap_row >= 0) S.x_hist[(snap_row * S.n + ccol) * L + l] = xn;
         }
     }
     // Untouched columns: decay only. With L a multiple of 4 and 16-byte
@@ -479,7 +484,8 @@ __device__ __forceinline__ void sparse_update(const Sparse& S, uint64_t h, int w
     }
 }
 
-// Clear the bucket counts of outer h (every tail entry clears its column).
+// Clear the bucket counts of outer h (every tail entry clears its column) and
+// its tail list.
 __device__ __forceinline__ void sparse_clear_buckets(const Sparse& S, uint64_t h, int gtid,
                                                      int nthreads) {
     const int slot = slot_of(h);
@@ -491,6 +497,7 @@ __device__ __forceinline__ void sparse_clear_buckets(const Sparse& S, uint64_t h
         const int t = (int)(e / S.maxlen), kk = (int)(e - (int64_t)t * S.maxlen);
         if (kk < tlen[t]) bcnt[tcol[e]] = 0u;
     }
+    if (gtid == 0) S.tlcnt[h & 1] = 0u;
 }
 
 // Residual corrections for lanes [l0, l0 + nl), nl <= kLanesPerRecWG, by the
