@@ -35,11 +35,16 @@ __global__ void k_set_lanes(LaneParams p, int L, double* lbeta, float* lbs) {
     }
 }
 
+// LDS: lane deltas and decay powers of the recurrence, then the per-wave
+// head-row buffers of the gather, which the recurrence workgroups use for
+// their reduction buffer instead (phases never overlap in a workgroup).
 __host__ __device__ inline size_t sparse_lds_bytes(int sb, int s, int acc_bytes, int Hp) {
     size_t off = (size_t)sb * kLanesPerRecWG * acc_bytes;
     off += (size_t)kLanesPerRecWG * (s + 1) * acc_bytes;
     off = (off + 15) & ~(size_t)15;
-    off += (size_t)kNW * Hp * 4;
+    const size_t rows = (size_t)kNW * Hp * 4;
+    const size_t red = (size_t)kRecRows * kLanesPerRecWG * (kNT / 4) * acc_bytes;
+    off += rows > red ? rows : red;
     // the head-panel Gram phase reuses the same memory
     return off < kGramLds ? kGramLds : off;
 }
@@ -64,6 +69,7 @@ __global__ __launch_bounds__(kNT) void k_sparse_fit(Sparse S, uint64_t h0, int64
     off = (off + 15) & ~(size_t)15;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float* hrow = reinterpret_cast<float*>(lds + off) + (size_t)wave * S.Hp;
+    ACC* red = reinterpret_cast<ACC*>(lds + off);
     // outside the recurrence the lane deltas' space holds one row of G per wave
     float* rowbuf = reinterpret_cast<float*>(lds) + (size_t)wave * S.sb;
 
@@ -96,7 +102,7 @@ __global__ __launch_bounds__(kNT) void k_sparse_fit(Sparse S, uint64_t h0, int64
         if (wg < R) {
             const int l0 = (wg / K) * NL;
             sparse_recurrence<ACC, kNT>(S, spick2(S.G, (int)(h & 1)), h, l0, min(NL, S.L - l0),
-                                        wg % K, K, dl, pw, spin);
+                                        wg % K, K, dl, pw, red, spin);
             if (wg == 0) mark(1);
         } else {
             const int w0 = (wg - R) * kNW + wave, nw = (nb - R) * kNW;

@@ -500,28 +500,48 @@ __device__ __forceinline__ void sparse_clear_buckets(const Sparse& S, uint64_t h
     if (gtid == 0) S.tlcnt[h & 1] = 0u;
 }
 
+// Rows of a recurrence pass and 16-byte prefix pieces per thread and batch.
+constexpr int kRecRows = 8;
+constexpr int kRecPieces = 2;
+
+// Value of the lane whose index differs in bit 0 (CTRL 0xB1) or bit 1 (CTRL
+// 0x4E) within each group of four lanes (DPP quad permutation).
+template <int CTRL>
+__device__ __forceinline__ float quad_perm(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double quad_perm(double v) {
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)x, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // Residual corrections for lanes [l0, l0 + nl), nl <= kLanesPerRecWG, by the
 // K workgroups of one lane group; workgroup k of the group owns rows
-// [k b/K, (k+1) b/K) of every row block. In step j each computes z_j and
-// delta_j of its own rows (every 16-byte piece of a G row prefix is loaded
-// once and applied to all lanes of the group), publishes the deltas as tagged
-// words and collects those of the other rows before step j + 1. The owner of
-// a word clears it after the grid barrier that follows the recurrence, so
-// every outer iteration starts from cleared words.
-// LDS: dl (kLanesPerRecWG x sb ACC, lane-major), pw (kLanesPerRecWG x (s+1) ACC).
+// [k b/K, (k+1) b/K) of every row block. In step j each takes its rows in
+// passes of kRecRows: every thread covers all rows of the pass for its own
+// 16-byte pieces of the row prefix (so each delta it reads from LDS serves
+// all the rows), the per-thread sums are added in a fixed order through LDS
+// (`red`), and one thread per (row, lane) forms z_j and delta_j. The deltas
+// are published as tagged words and those of the other rows collected before
+// step j + 1; the first batch of G pieces, the margins and the labels of the
+// next step are loaded while waiting. The owner of a word clears it after the
+// grid barrier that follows the recurrence, so every outer iteration starts
+// from cleared words.
+// LDS: dl (kLanesPerRecWG x sb ACC, lane-major), pw (kLanesPerRecWG x (s+1)
+// ACC), red (kRecRows x kLanesPerRecWG x NT / 4 ACC).
 template <typename ACC, int NT>
 __device__ __forceinline__ void sparse_recurrence(const Sparse& S, const float* G, uint64_t h,
                                                   int l0, int nl, int k, int K, ACC* dl, ACC* pw,
-                                                  unsigned long long spin) {
+                                                  ACC* red, unsigned long long spin) {
     constexpr int NL = kLanesPerRecWG;
+    constexpr int RC = kRecRows, PB = kRecPieces;
+    static_assert(RC * NL * 8 == NT, "one finishing group of 8 threads per (row, lane)");
     const int tid = threadIdx.x;
     const int b = S.b, s = S.s, sb = S.sb, L = S.L;
     const int RB = b / K, q_lo = k * RB;
-    // threads per row: a power of two, at most one wave
-    int TPR = 1;
-    while (TPR < 64 && 2 * TPR * RB <= NT) TPR *= 2;
-    const int RPP = NT / TPR;
-    const int sub = tid % TPR;
     if (tid < NL) {
         ACC p = 1;
         const ACC be = tid < nl ? (ACC)S.lbeta[l0 + tid] : (ACC)1;
@@ -530,86 +550,113 @@ __device__ __forceinline__ void sparse_recurrence(const Sparse& S, const float* 
     __syncthreads();
     const ACC alpha = (ACC)S.alpha_d;
     const float* yI = spick3(S.yI, slot_of(h));
-    // First batch of G pieces, residuals and labels of a step's first row
-    // pass, loaded one step ahead (while the deltas of the step before are
-    // exchanged).
-    float4 gp[kRB];
-    float rp[NL], yp;
+    // finishing thread of (row o / NL, lane o % NL) of a pass: part == 0
+    const int o = tid >> 3, part = tid & 7;
+    const int orow = o / NL, olane = o - orow * NL;
+    // First batch of G pieces of a step's first pass, and the finishing
+    // threads' margins and labels, loaded one step ahead.
+    float4 gp[RC][PB];
+    float rp = 0.f, yp = 0.f;
     auto load_first = [&](int jj) {
         const int nvj = max((jj * b) >> 2, 1);
-        const int t = jj * b + q_lo + min(tid / TPR, RB - 1);
-        const float4* g4 = reinterpret_cast<const float4*>(G + (int64_t)t * sb);
 #pragma unroll
-        for (int u = 0; u < kRB; ++u) gp[u] = g4[min(sub + u * TPR, nvj - 1)];
+        for (int rr = 0; rr < RC; ++rr) {
+            const int t = jj * b + q_lo + min(rr, RB - 1);
+            const float4* g4 = reinterpret_cast<const float4*>(G + (int64_t)t * sb);
 #pragma unroll
-        for (int l = 0; l < NL; ++l) rp[l] = S.r[(int64_t)t * L + l0 + min(l, nl - 1)];
+            for (int pb = 0; pb < PB; ++pb) gp[rr][pb] = g4[min(tid + pb * NT, nvj - 1)];
+        }
+        const int t = jj * b + q_lo + min(orow, RB - 1);
+        rp = S.r[(int64_t)t * L + l0 + min(olane, nl - 1)];
         yp = yI[t];
     };
     load_first(0);
     for (int j = 0; j < s; ++j) {
         const int nv = (j * b) >> 2;   // 16-byte pieces of the row prefix
-        for (int q0 = 0; q0 < RB; q0 += RPP) {
-            const int q = q0 + tid / TPR;
-            const bool active = q < RB;
-            const int t = j * b + q_lo + min(q, RB - 1);
-            ACC acc[NL];
+        for (int q0 = 0; q0 < RB; q0 += RC) {
+            ACC acc[RC][NL];
 #pragma unroll
-            for (int l = 0; l < NL; ++l) acc[l] = 0;
-            float rr[NL], yv;
-            if (q0 == 0) {
+            for (int rr = 0; rr < RC; ++rr)
 #pragma unroll
-                for (int l = 0; l < NL; ++l) rr[l] = rp[l];
-                yv = yp;
-            } else {
+                for (int l = 0; l < NL; ++l) acc[rr][l] = 0;
+            for (int v0 = tid; v0 < nv; v0 += PB * NT) {
+                float4 g[RC][PB];
+                if (q0 == 0 && v0 == tid) {
 #pragma unroll
-                for (int l = 0; l < NL; ++l) rr[l] = S.r[(int64_t)t * L + l0 + min(l, nl - 1)];
-                yv = yI[t];
-            }
-            const float4* g4 = reinterpret_cast<const float4*>(G + (int64_t)t * sb);
-            for (int base = sub; base < nv; base += kRB * TPR) {
-                float4 g[kRB];
-                if (q0 == 0 && base == sub) {
+                    for (int rr = 0; rr < RC; ++rr)
 #pragma unroll
-                    for (int u = 0; u < kRB; ++u) g[u] = gp[u];
+                        for (int pb = 0; pb < PB; ++pb) g[rr][pb] = gp[rr][pb];
                 } else {
 #pragma unroll
-                    for (int u = 0; u < kRB; ++u) g[u] = g4[min(base + u * TPR, nv - 1)];
+                    for (int rr = 0; rr < RC; ++rr) {
+                        const int t = j * b + q_lo + min(q0 + rr, RB - 1);
+                        const float4* g4 = reinterpret_cast<const float4*>(G + (int64_t)t * sb);
+#pragma unroll
+                        for (int pb = 0; pb < PB; ++pb) g[rr][pb] = g4[min(v0 + pb * NT, nv - 1)];
+                    }
                 }
 #pragma unroll
-                for (int u = 0; u < kRB; ++u) {
-                    const int v = base + u * TPR;
-                    if (v < nv) {
-                        const int e = 4 * v;
-                        const int i = e / b;
+                for (int pb = 0; pb < PB; ++pb) {
+                    const int v = v0 + pb * NT;
+                    const int e = 4 * min(v, nv - 1);
+                    const int i = e / b;
+                    ACC dv[NL][4], wl[NL];
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) dv[l][q] = dl[l * sb + e + q];
+                        wl[l] = v < nv ? pw[l * (s + 1) + (j - 1 - i)] : (ACC)0;
+                    }
+#pragma unroll
+                    for (int rr = 0; rr < RC; ++rr)
 #pragma unroll
                         for (int l = 0; l < NL; ++l) {
-                            const ACC* d = dl + l * sb + e;   // lane-major: 4 consecutive rows
-                            const ACC part = (ACC)g[u].x * d[0] + (ACC)g[u].y * d[1] +
-                                             (ACC)g[u].z * d[2] + (ACC)g[u].w * d[3];
-                            acc[l] += pw[l * (s + 1) + (j - 1 - i)] * part;
+                            const ACC pt = (ACC)g[rr][pb].x * dv[l][0] + (ACC)g[rr][pb].y * dv[l][1] +
+                                           (ACC)g[rr][pb].z * dv[l][2] + (ACC)g[rr][pb].w * dv[l][3];
+                            acc[rr][l] += wl[l] * pt;
                         }
-                    }
                 }
             }
+            // fixed-order sum over the threads: groups of four lanes first
+            // (DPP), then thread (o, part) adds eight consecutive group sums
+            // of output o, then the eight parts
+            constexpr int NG = NT / 4;
 #pragma unroll
-            for (int l = 0; l < NL; ++l) acc[l] = group_sum_rt(acc[l], TPR);
-            // every thread of the row group holds the sums; thread l % TPR
-            // finishes lane l
-            if (active) {
+            for (int rr = 0; rr < RC; ++rr)
 #pragma unroll
                 for (int l = 0; l < NL; ++l) {
-                    if ((l & (TPR - 1)) != sub) continue;
-                    ACC d = 0;
-                    if (l < nl) {
-                        const ACC z = pw[l * (s + 1) + j] * (ACC)rr[l] + alpha * acc[l];
-                        d = (ACC)yv / ((ACC)1 + exp((ACC)yv * z));
-                        if (!isfinite(z)) raise_flag(S.flags, FLAG_NONFINITE);
-                        S.c[(int64_t)t * L + l0 + l] = (float)(pw[l * (s + 1) + (s - 1 - j)] * d);
-                        if (K > 1 && j + 1 < s) pub_put(S.pub + 2 * ((int64_t)t * L + l0 + l), d);
-                    }
-                    dl[l * sb + t] = d;
+                    ACC a = acc[rr][l];
+                    a += quad_perm<0xB1>(a);
+                    a += quad_perm<0x4E>(a);
+                    if ((tid & 3) == 0) red[(rr * NL + l) * NG + (tid >> 2)] = a;
                 }
+            __syncthreads();
+            ACC tot = 0;
+#pragma unroll
+            for (int m = 0; m < NG / 8; ++m) tot += red[o * NG + part * (NG / 8) + m];
+            tot += shfl_xor(tot, 1);
+            tot += shfl_xor(tot, 2);
+            tot += shfl_xor(tot, 4);
+            const int q = q0 + orow;
+            if (part == 0 && q < RB) {
+                const int t = j * b + q_lo + q;
+                const int l = olane;
+                float rv = rp, yv = yp;
+                if (q0 != 0) {
+                    rv = S.r[(int64_t)t * L + l0 + min(l, nl - 1)];
+                    yv = yI[t];
+                }
+                ACC d = 0;
+                if (l < nl) {
+                    const ACC z = pw[l * (s + 1) + j] * (ACC)rv + alpha * tot;
+                    d = (ACC)yv / ((ACC)1 + exp((ACC)yv * z));
+                    if (!isfinite(z)) raise_flag(S.flags, FLAG_NONFINITE);
+                    S.c[(int64_t)t * L + l0 + l] = (float)(pw[l * (s + 1) + (s - 1 - j)] * d);
+                    if (K > 1 && j + 1 < s) pub_put(S.pub + 2 * ((int64_t)t * L + l0 + l), d);
+                }
+                dl[l * sb + t] = d;
             }
+            __syncthreads();   // `red` is reused by the next pass
         }
         if (j + 1 < s) load_first(j + 1);
         if (K > 1 && j + 1 < s) {
@@ -624,9 +671,9 @@ __device__ __forceinline__ void sparse_recurrence(const Sparse& S, const float* 
 #pragma unroll
                 for (int u = 0; u < kP; ++u) {
                     const int w = w0 + u * NT;
-                    const int q = w / NL, l = w - q * NL;
-                    need[u] = w < b * NL && (q < q_lo || q >= q_lo + RB) && l < nl;
-                    pp[u] = S.pub + 2 * ((int64_t)(j * b + min(q, b - 1)) * L + l0 + min(l, nl - 1));
+                    const int qq = w / NL, l = w - qq * NL;
+                    need[u] = w < b * NL && (qq < q_lo || qq >= q_lo + RB) && l < nl;
+                    pp[u] = S.pub + 2 * ((int64_t)(j * b + min(qq, b - 1)) * L + l0 + min(l, nl - 1));
                     d[u] = 0;
                 }
                 unsigned long long n = 0;
@@ -649,9 +696,9 @@ __device__ __forceinline__ void sparse_recurrence(const Sparse& S, const float* 
 #pragma unroll
                 for (int u = 0; u < kP; ++u) {
                     const int w = w0 + u * NT;
-                    const int q = w / NL;
-                    if (w < b * NL && (q < q_lo || q >= q_lo + RB))
-                        dl[(w - q * NL) * sb + j * b + q] = d[u];
+                    const int qq = w / NL;
+                    if (w < b * NL && (qq < q_lo || qq >= q_lo + RB))
+                        dl[(w - qq * NL) * sb + j * b + qq] = d[u];
                 }
             }
         }

@@ -108,3 +108,37 @@ def test_one_outer_iteration_within_theorem_bound(cg, c1, fmt, b, s):
     print(f"\n[thm5.1] fmt={fmt} b={b} s={s} u_A={u_A:.2e} error={err:.3e} bound={res['bound']:.3e}"
           f" ratio={err / res['bound']:.3f}")
     assert err <= res["bound"]
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "f16", "fp8"])
+@pytest.mark.parametrize("b,s", [(32, 8), (128, 8)])
+def test_one_outer_iteration_within_theorem_bound_bounded_entries(cg, c1, fmt, b, s):
+    """The same check on rows whose entries all have magnitudes within a factor
+    of two of each other (signs and labels of the 4096 x 256 workload), so no
+    stored element is subnormal and u_A is the format's own relative rounding
+    error (FP16 2^-11, FP8-e4m3 2^-4 with the row scale): the bound is then
+    tight enough to be informative for every format."""
+    eta, seed = 0.5, 7
+    mag = np.random.default_rng(11).uniform(0.5, 1.0, size=c1.X.shape)
+    Xn = normalize_rows(np.sign(c1.X + (c1.X == 0)) * mag)
+    X32 = Xn.astype(np.float32)
+    X, exact, keep = _store(cg, X32, fmt)
+    u_A = float(np.max(np.abs(exact - Xn) / np.abs(Xn)))
+    assert u_A <= {"bf16": 2.0 ** -8, "f16": 2.0 ** -11, "fp8": 2.0 ** -4}[fmt] * 1.01
+    x0 = (np.random.default_rng(4).standard_normal(256) * 0.5).astype(np.float32)
+    x = _dev(x0)
+    y = _dev(c1.y)
+    ws = cg.casgd_step(X, y, x, eta, 0.0, b, s, seed, 0)
+    cg.casgd_check(ws)
+    xg = x.cpu().numpy().astype(np.float64)
+    idx = R.sample_indices(seed, 0, s * b, Xn.shape[0])
+    n, sb = 256, s * b
+    u_c = R.U_FP64 if sb >= 512 else U32
+    res = R.local_error_bound(Xn[idx], x0.astype(np.float64), c1.y[idx].astype(np.float64), b, s,
+                              eta, u_A=u_A, gamma_r=R.gamma(n + 2, U32),
+                              gamma_G=R.gamma(n + 2, U32), u_c=u_c, u_sigma=u_c,
+                              gamma_g=R.gamma(sb + 3, U32), u_x=U32)
+    err = float(np.linalg.norm(xg - res["x_exact"]))
+    print(f"\n[thm5.1 bounded] fmt={fmt} b={b} s={s} u_A={u_A:.2e} error={err:.3e} "
+          f"bound={res['bound']:.3e} ratio={err / res['bound']:.3f}")
+    assert err <= res["bound"]
