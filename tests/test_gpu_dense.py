@@ -346,3 +346,36 @@ def test_colstats_vs_oracle(cg, fmt):
     got = cg.casgd_colstats(Xs).cpu().numpy().astype(np.float64)
     ref = R.column_stats(exact)
     assert np.allclose(got, ref, rtol=1e-5, atol=1e-7)
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_c2_scale_sampled_check(cg, storage):
+    """Full-size dense workload (2^20 x 2048 FP32, b = 64, s = 16, lambda =
+    1e-5, eta = 2) in the launch configuration the benchmark times (fused,
+    automatic form and grid): six outer iterations against the oracle, which
+    reads only the sampled rows (for BF16 storage, of the stored values)."""
+    from workloads import dense_c2
+    p = dense_c2(42, m=1 << 20, n=2048, m_test=1)
+    b, s, H, eta, lam, seed = 64, 16, 6, 2.0, 1e-5, 42
+    X32 = torch.from_numpy(p.X).cuda()
+    if storage == "f32":
+        X = cg.dense_matrix(X32)
+        Xo = p.X
+    else:
+        v, sc = cg.casgd_quantize(X32, cg.BF16)
+        X = cg.dense_matrix(v, sc, n=2048)
+        # the oracle reads only the sampled rows: give it their stored values
+        # (in place: the FP32 copy is on the device already)
+        idx = np.unique(R.sample_indices(seed, 0, H * s * b, p.X.shape[0]))
+        _, _, exact = R.quantize(p.X[idx], "bf16")
+        p.X[idx] = exact
+        Xo = p.X
+    y = torch.from_numpy(p.y).cuda()
+    x = torch.zeros(2048, device="cuda")
+    ws = cg.casgd_fit(X, y, x, eta, lam, b, s, seed, 0, H)
+    cg.casgd_check(ws)
+    xg = x.cpu().numpy().astype(np.float64)
+    xo = R.casgd(Xo, p.y, np.zeros(2048), eta, lam, b, s, seed, 0, H)
+    err = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+    print(f"\n[c2 scale] storage={storage} outer={H} rel_err={err:.3e}")
+    assert err < 1e-4
