@@ -77,3 +77,42 @@ def test_batch_explicit_groups(cg):
         cg.casgd_fit(q["X"], q["y"], solo, q["eta"], q["lam"], q["b"], q["s"], q["seed"], 0,
                      q["H"], opts=o)
         assert torch.equal(solo, xs[i]), i
+
+
+def test_full_size_uneven_batch_sampled_check(cg):
+    """The full uneven workload shape: 64 problems, m log-uniform in
+    [10^4, 2*10^5], n in [128, 4096], column-scale spread up to 10^3, BF16
+    storage, b = 64, s = 16, all in one batched launch (automatic groups and
+    forms). Three outer iterations; four problems (the smallest and largest
+    m and n) checked against the oracle on the stored values of their sampled
+    rows, which is all the oracle reads."""
+    b, s, H, lam = 64, 16, 3, 1e-5
+    specs = uneven_problem_specs(64, 2024)
+    pick = {int(np.argmin([q["m"] for q in specs])), int(np.argmax([q["m"] for q in specs])),
+            int(np.argmin([q["n"] for q in specs])), int(np.argmax([q["n"] for q in specs]))}
+    batch, keep = [], {}
+    for i, sp in enumerate(specs):
+        p = uneven_problem(sp)
+        stored, scale = cg.casgd_quantize(torch.from_numpy(p.X).cuda(), cg.BF16)
+        X = cg.dense_matrix(stored, scale, n=p.n)
+        # step size from the mean squared row norm of a row sample (as the
+        # driver of the learned preconditioner does for its plain baseline)
+        rows = p.X[:: max(1, p.m // 2048)].astype(np.float64)
+        eta = 0.5 / float((rows ** 2).sum(axis=1).mean())
+        x = torch.zeros(p.n, device="cuda")
+        batch.append(dict(X=X, y=torch.from_numpy(p.y).cuda(), x=x, eta=eta, lam=lam, b=b, s=s,
+                          seed=300 + i, n_outer=H))
+        if i in pick:
+            idx = np.unique(R.sample_indices(300 + i, 0, H * s * b, p.m))
+            _, _, exact = R.quantize(p.X[idx], "bf16")
+            p.X[idx] = exact
+            keep[i] = (p, eta)
+        del p
+    for ws in cg.casgd_fit_batch(batch):
+        cg.casgd_check(ws)
+    for i, (p, eta) in keep.items():
+        xo = R.casgd(p.X, p.y, np.zeros(p.n), eta, lam, b, s, 300 + i, 0, H)
+        xg = batch[i]["x"].cpu().numpy().astype(np.float64)
+        err = np.linalg.norm(xg - xo) / max(np.linalg.norm(xo), 1e-30)
+        print(f"\n[c5 scale] problem {i} m={p.m} n={p.n} rel_err={err:.3e}")
+        assert err < 1e-4, i
