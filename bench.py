@@ -334,6 +334,72 @@ def c4_bench(cg, steps: int, warmup: int):
             "test_loss_by_lane": [round(float(v), 6) for v in losses]}
 
 
+def c5_batch_bench(cg, H: int, count: int = 64):
+    """The uneven workload at full size: `count` problems, m log-uniform in
+    [1e4, 2e5], n in [128, 4096], BF16 storage, b = 64, s = 16, H outer
+    iterations each. One batched launch (automatic groups) against the same
+    problems launched one after another; both timed with HIP events."""
+    import torch
+    from workloads import uneven_problem, uneven_problem_specs
+    b, s, lam = 64, 16, 1e-5
+    t = time.perf_counter()
+    probs = []
+    for i, sp in enumerate(uneven_problem_specs(count, 2024)):
+        p = uneven_problem(sp)
+        stored, scale = cg.casgd_quantize(torch.from_numpy(p.X).cuda(), cg.BF16)
+        rows = p.X[:: max(1, p.m // 2048)].astype(np.float64)
+        eta = 0.5 / float((rows ** 2).sum(axis=1).mean())
+        probs.append(dict(X=cg.dense_matrix(stored, scale, n=p.n), y=torch.from_numpy(p.y).cuda(),
+                          n=p.n, m=p.m, eta=eta, seed=300 + i))
+        del p
+    log(f"[c5-batch] {count} problems generated and stored in BF16 in {time.perf_counter() - t:.1f}s")
+    stream = torch.cuda.current_stream()
+    wss = [cg.workspace(cg.casgd_workspace_size(q["X"], b, s)) for q in probs]
+
+    def batch_run(h0, nh):
+        xs = [torch.zeros(q["n"], device="cuda") for q in probs]
+        batch = [dict(X=q["X"], y=q["y"], x=xs[i], eta=q["eta"], lam=lam, b=b, s=s,
+                      seed=q["seed"], outer_begin=h0, n_outer=nh, ws=wss[i])
+                 for i, q in enumerate(probs)]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        cg.casgd_fit_batch(batch, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        for ws in wss:
+            cg.casgd_check(ws)
+        return e0.elapsed_time(e1)
+
+    def solo_run(h0, nh):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        xs = [torch.zeros(q["n"], device="cuda") for q in probs]
+        e0.record(stream)
+        for i, q in enumerate(probs):
+            cg.casgd_fit(q["X"], q["y"], xs[i], q["eta"], lam, b, s, q["seed"], h0, nh, ws=wss[i],
+                         stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        for ws in wss:
+            cg.casgd_check(ws)
+        return e0.elapsed_time(e1)
+
+    batch_run(0, 2)
+    solo_run(0, 2)
+    ms_b = batch_run(0, H)
+    ms_s = solo_run(0, H)
+    updates = count * s * H
+    log(f"[c5-batch] batched {ms_b:.2f} ms, one launch per problem {ms_s:.2f} ms for "
+        f"{updates} SGD updates")
+    return {"metric": "SGD updates/s over 64 uneven problems (one batched launch)",
+            "value": round(updates / (ms_b * 1e-3), 1), "unit": "SGD updates/s",
+            "solo_launches_value": round(updates / (ms_s * 1e-3), 1),
+            "speedup_vs_solo_launches": round(ms_s / ms_b, 3), "outer_per_problem": H,
+            "dtype": "bf16", "data": "synthetic",
+            "config": {"workload": f"{count} uneven dense problems, m 1e4..2e5, n 128..4096, "
+                                   f"column-scale spread <= 1e3, BF16 X, b={b}, s={s}"},
+            "problems": [dict(m=q["m"], n=q["n"]) for q in probs]}
+
+
 def c5_bench(cg, n_train: int, n_eval: int, epochs: float = 2.0):
     """Learned diagonal preconditioner on uneven dense problems (BF16 X, s = 16,
     b = 64): MLP trained by the library's kernels on targets from plain runs,
@@ -444,6 +510,8 @@ def main():
     ap.add_argument("--source-hash", action="store_true")
     ap.add_argument("--c4", action="store_true", help="sparse lambda-path workload only")
     ap.add_argument("--c5", action="store_true", help="learned preconditioner workload only")
+    ap.add_argument("--c5-batch", action="store_true",
+                    help="uneven problems at full size: batched vs one launch per problem")
     ap.add_argument("--c5-train", type=int, default=64)
     ap.add_argument("--c5-eval", type=int, default=16)
     args = ap.parse_args()
@@ -466,6 +534,10 @@ def main():
         return
     if args.c5:
         print(json.dumps(c5_bench(cg, args.c5_train, args.c5_eval)), flush=True)
+        return
+    if args.c5_batch:
+        H = args.steps if args.steps is not None else 32
+        print(json.dumps(c5_batch_bench(cg, H)), flush=True)
         return
     if args.c4:
         K = args.steps if args.steps is not None else 64
