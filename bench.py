@@ -410,7 +410,7 @@ def c5_bench(cg, n_train: int, n_eval: int, epochs: float = 2.0):
     from paper_2606_18463_amd import learned as Lm
     from workloads import uneven_problem, uneven_problem_specs
     b, s, lam = 64, 16, 1e-5
-    rng = dict(m_range=(1e4, 5e4), n_range=(128, 1024), spread_range=(1.0, 1e3))
+    rng = dict(m_range=(1e4, 2e5), n_range=(128, 4096), spread_range=(1.0, 1e3))
     t0 = time.perf_counter()
     stats, tds, tetas = [], [], []
     for sp in uneven_problem_specs(n_train, 101, **rng):
@@ -512,8 +512,8 @@ def main():
     ap.add_argument("--c5", action="store_true", help="learned preconditioner workload only")
     ap.add_argument("--c5-batch", action="store_true",
                     help="uneven problems at full size: batched vs one launch per problem")
-    ap.add_argument("--c5-train", type=int, default=64)
-    ap.add_argument("--c5-eval", type=int, default=16)
+    ap.add_argument("--c5-train", type=int, default=256)
+    ap.add_argument("--c5-eval", type=int, default=64)
     args = ap.parse_args()
     if args.source_hash:
         print(sources_hash())
