@@ -320,8 +320,8 @@ __device__ __forceinline__ void sparse_margins(const Sparse& S, uint64_t h, floa
 // Update of outer h for all lanes: x <- beta^s x + alpha * Y^T c.
 //  * head columns: one workgroup per (16 head columns, 16 lanes) tile
 //    computes Yh^T c (H x rows times rows x lanes) with FP32 MFMA 16x16x4;
-//  * tail columns present in the block: one wave per column sums its bucket
-//    in increasing t for every lane (see below);
+//  * tail columns present in the block: one wave (or half-wave) per column
+//    sums its bucket in increasing t for every lane (see below);
 //  * all other columns: x <- beta^s x.
 __device__ __forceinline__ void sparse_update(const Sparse& S, uint64_t h, int wave_id, int nwaves,
                                               int gtid, int nthreads, int64_t snap_row,
@@ -395,41 +395,51 @@ __device__ __forceinline__ void sparse_update(const Sparse& S, uint64_t h, int w
         }
         __syncthreads();
     }
-    // Tail columns of the block, from the tail list: one wave per column. Lane
-    // q ranks bucket entry q by (t, bucket slot) and stores it at its rank in
-    // the wave's LDS scratch, then lane l (one per lambda lane) adds the
-    // entries in increasing t, four loads in flight at a time.
+    // Tail columns of the block, from the tail list: with at most 32 lanes
+    // (and room for two scratch lists) each half-wave takes a column, else the
+    // whole wave. Lane q of the group ranks bucket entries q and q + width by
+    // (t, bucket slot) and stores them at their ranks in the group's LDS
+    // scratch, then lane l (one per lambda lane) adds the entries in
+    // increasing t, four loads in flight at a time.
     const int ncol = min((int)S.tlcnt[h & 1], (int)S.n);
     const int32_t* tl = spick2(S.tlist, (int)(h & 1));
-    for (int ci = wave_id; ci < ncol; ci += nwaves) {
-        const int ccol = tl[ci];
-        const int cnt = min((int)bcnt[ccol], kBucketCap);
-        const int2 en = lane < cnt ? bent[(int64_t)ccol * kBucketCap + lane]
-                                   : make_int2(0x7fffffff, 0);
-        int rank = 0;
+    const int cpw = (L <= 32 && S.Hp >= 256) ? 2 : 1;   // columns per wave
+    const int wd = kWave / cpw;                          // lanes per column
+    const int half = lane / wd, hl = lane - half * wd;
+    int2* srt = sorted + half * kBucketCap;
+    for (int c0 = wave_id * cpw; c0 < ncol; c0 += nwaves * cpw) {
+        const int ci = c0 + half;
+        const int ccol = tl[min(ci, ncol - 1)];
+        const int cnt = ci < ncol ? min((int)bcnt[ccol], kBucketCap) : 0;
+        const int2* be = bent + (int64_t)ccol * kBucketCap;
+        const int2 none = make_int2(0x7fffffff, 0);
+        const int2 e0 = hl < cnt ? be[hl] : none;
+        const int2 e1 = hl + wd < cnt ? be[hl + wd] : none;
+        int r0 = 0, r1 = 0;
         for (int q = 0; q < cnt; ++q) {
-            const int tq = __shfl(en.x, q, kWave);
-            rank += (tq < en.x || (tq == en.x && q < lane)) ? 1 : 0;
+            const int tq = __shfl(q < wd ? e0.x : e1.x, q & (wd - 1), wd);
+            r0 += (tq < e0.x || (tq == e0.x && q < hl)) ? 1 : 0;
+            r1 += (tq < e1.x || (tq == e1.x && q < hl + wd)) ? 1 : 0;
         }
         wave_lds_sync();
-        if (lane < cnt) sorted[rank] = en;
+        if (hl < cnt) srt[r0] = e0;
+        if (hl + wd < cnt) srt[r1] = e1;
         wave_lds_sync();
-        const int l = lane;
-        if (l < L) {
+        const int l = hl;
+        if (ci < ncol && l < L) {
             float g = 0.f;
             int p = 0;
             for (; p + 4 <= cnt; p += 4) {
-                const int2 e0v = sorted[p], e1v = sorted[p + 1], e2v = sorted[p + 2],
-                           e3v = sorted[p + 3];
-                const float c0 = S.c[(int64_t)e0v.x * L + l], c1 = S.c[(int64_t)e1v.x * L + l],
-                            c2 = S.c[(int64_t)e2v.x * L + l], c3 = S.c[(int64_t)e3v.x * L + l];
-                g = fmaf(__int_as_float(e0v.y), c0, g);
-                g = fmaf(__int_as_float(e1v.y), c1, g);
-                g = fmaf(__int_as_float(e2v.y), c2, g);
-                g = fmaf(__int_as_float(e3v.y), c3, g);
+                const int2 e0v = srt[p], e1v = srt[p + 1], e2v = srt[p + 2], e3v = srt[p + 3];
+                const float c0v = S.c[(int64_t)e0v.x * L + l], c1v = S.c[(int64_t)e1v.x * L + l],
+                            c2v = S.c[(int64_t)e2v.x * L + l], c3v = S.c[(int64_t)e3v.x * L + l];
+                g = fmaf(__int_as_float(e0v.y), c0v, g);
+                g = fmaf(__int_as_float(e1v.y), c1v, g);
+                g = fmaf(__int_as_float(e2v.y), c2v, g);
+                g = fmaf(__int_as_float(e3v.y), c3v, g);
             }
             for (; p < cnt; ++p) {
-                const int2 ev = sorted[p];
+                const int2 ev = srt[p];
                 g = fmaf(__int_as_float(ev.y), S.c[(int64_t)ev.x * L + l], g);
             }
             const float xn = S.lbs[l] * S.x[(int64_t)ccol * L + l] + alpha * g;

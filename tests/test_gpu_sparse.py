@@ -105,6 +105,28 @@ def test_recurrence_split_rejects_bad_values(cg, small):
                               opts=cg.opts(rec_split=k), ws=ws)
 
 
+@pytest.mark.parametrize("L,m,nnz", [(40, 4000, 20.0), (4, 20000, 8.0)])
+def test_tail_update_one_column_per_wave(cg, L, m, nnz):
+    """The tail update's whole-wave form (more than 32 lanes; or a head panel
+    of 128 columns, which leaves room for one scratch list per wave: few
+    columns are frequent enough per block when m is large and rows short)
+    against the oracle."""
+    p = sparse_zipf_logreg(m, 3000, 13, nnz_mean=nnz)
+    X = _csr(cg, p)
+    y = _dev(p.y)
+    lams = list(np.geomspace(1e-5, 1e-2, L))
+    b, s, H = 16, 8, 30
+    ws = cg.casgd_sparse_prepare(X, b, s, L)
+    xl = torch.zeros(p.n, L, device="cuda")
+    cg.casgd_fit_path(X, y, xl, lams, 1.5, b, s, 9, 0, H, ws=ws)
+    cg.casgd_check(ws)
+    got = xl.cpu().numpy().astype(np.float64)
+    for l in (0, L - 1):
+        xo = R.casgd_csr(p.row_ptr, p.col_idx, p.values, p.n, p.y, np.zeros(p.n), 1.5, lams[l],
+                         b, s, 9, 0, H)
+        assert np.linalg.norm(got[:, l] - xo) / np.linalg.norm(xo) < 1e-4, l
+
+
 def test_sparse_equals_dense_on_densified(cg, small):
     p = small
     D = p.to_dense()
