@@ -407,7 +407,11 @@ __device__ __forceinline__ void sparse_update(const Sparse& S, uint64_t h, int w
     const int wd = kWave / cpw;                          // lanes per column
     const int half = lane / wd, hl = lane - half * wd;
     int2* srt = sorted + half * kBucketCap;
-    for (int c0 = wave_id * cpw; c0 < ncol; c0 += nwaves * cpw) {
+    // when the head tiles occupy only some workgroups, the others' waves take
+    // the tail columns (the head tile costs about as much as their share)
+    const int hw = ht * lt < (int)gridDim.x ? ht * lt * kNW : 0;   // waves with a head tile
+    const int trank = wave_id - hw, ntw = nwaves - hw;
+    for (int c0 = trank * cpw; trank >= 0 && c0 < ncol; c0 += ntw * cpw) {
         const int ci = c0 + half;
         const int ccol = tl[min(ci, ncol - 1)];
         const int cnt = ci < ncol ? min((int)bcnt[ccol], kBucketCap) : 0;
