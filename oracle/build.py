@@ -1,6 +1,6 @@
 """Compile the C part of the oracle into ``oracle/liboracle.so`` (gcc, OpenMP).
 
-Test infrastructure: the oracle is a checker, never part of the product path.
+Test infrastructure: the oracle only verifies results and is never part of the product path.
 """
 from __future__ import annotations
 
