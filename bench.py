@@ -334,6 +334,25 @@ def c4_bench(cg, steps: int, warmup: int):
             "test_loss_by_lane": [round(float(v), 6) for v in losses]}
 
 
+def autotune_bench(cg, wl):
+    """The tuner on the 2^20 x 2048 FP32 workload at b = 64: every candidate
+    (s, execution form) it measures and the choice it stores."""
+    from paper_2606_18463_amd import autotune as at
+    X, y, _keep = upload(cg, wl, "f32")
+    res = []
+    c = at.tune(X, y, B_C2, ETA_C2, LAMBDA_C2, SEED, s_grid=(1, 4, 16, 32),
+                budget_s=0.05, results=res)
+    name = {(0, 1): "fused v1", (0, 2): "fused v2", (0, 3): "fused v3", (2, 0): "stream"}
+    for r in res:
+        log(f"[autotune] s={r.s:2d} {name[(r.exec_mode, r.variant)]:9s} {r.updates_per_s:10.0f} updates/s")
+    return {"metric": "autotuner candidates (SGD updates/s)",
+            "workload": f"dense {wl.m}x{wl.n} FP32, lambda={LAMBDA_C2}, eta={ETA_C2}", "b": B_C2,
+            "choice": {"s": c.s, "form": name[(c.exec_mode, c.variant)],
+                       "updates_per_s": round(c.updates_per_s, 1)},
+            "candidates": [{"s": r.s, "form": name[(r.exec_mode, r.variant)],
+                            "updates_per_s": round(r.updates_per_s, 1)} for r in res]}
+
+
 def c5_batch_bench(cg, H: int, count: int = 64):
     """The uneven workload at full size: `count` problems, m log-uniform in
     [1e4, 2e5], n in [128, 4096], BF16 storage, b = 64, s = 16, H outer
@@ -510,6 +529,8 @@ def main():
     ap.add_argument("--source-hash", action="store_true")
     ap.add_argument("--c4", action="store_true", help="sparse lambda-path workload only")
     ap.add_argument("--c5", action="store_true", help="learned preconditioner workload only")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the autotuner on the dense workload and list its candidates")
     ap.add_argument("--c5-batch", action="store_true",
                     help="uneven problems at full size: batched vs one launch per problem")
     ap.add_argument("--c5-train", type=int, default=256)
@@ -545,6 +566,9 @@ def main():
         return
 
     s, b, n, dtype = args.s, B_C2, args.n, args.dtype
+    if args.autotune:
+        print(json.dumps(autotune_bench(cg, Workload(args.m, n))), flush=True)
+        return
     wl = Workload(args.m, n, with_test=args.eta_sweep or not args.no_ttt)
     if args.eta_sweep:
         res = eta_sweep(cg, wl, [2.0 ** k for k in range(-2, 7)])

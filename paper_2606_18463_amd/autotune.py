@@ -7,12 +7,15 @@ updates per second over the launch choices the library exposes:
   * s (outer block size; s*b <= 4096),
   * execution mode: the fused persistent launch (variant 1: every workgroup
     runs the recurrence; variant 2: one workgroup runs it while the others
-    build the next Gram matrix) or the stream-ordered kernel sequence,
+    build the next Gram matrix; variant 3: the chain and helper workgroups
+    run it while the others build the next Gram matrix) or the
+    stream-ordered kernel sequence,
   * the fused launch's grid size.
 
-Results persist in a JSON table keyed by (dtype, b, n bucket, m bucket) with
-power-of-two buckets, so similar shapes reuse one measurement. The batched
-launch takes s and the variant per problem from the same table.
+Candidates a shape does not support (variant 3 needs b in {16, 32, 64, 128}
+and s > 1) are skipped. Results persist in a JSON table keyed by (dtype, b,
+n bucket, m bucket) with power-of-two buckets, so similar shapes reuse one
+measurement.
 """
 from __future__ import annotations
 
@@ -25,7 +28,7 @@ import paper_2606_18463_amd as cg
 
 S_GRID = (1, 2, 4, 8, 16, 32, 64)
 # (exec_mode, fused_variant): 0 = fused persistent launch, 2 = stream-ordered
-MODES = ((0, 1), (0, 2), (2, 0))
+MODES = ((0, 1), (0, 2), (0, 3), (2, 0))
 
 
 @dataclass
@@ -68,8 +71,9 @@ def _time_fit(X, y, b, s, eta, lam, seed, o, budget_s: float) -> float:
 
 def tune(X, y, b: int, eta: float = 0.5, lam: float = 1e-5, seed: int = 0,
          s_grid=S_GRID, modes=MODES, grids=(0,), budget_s: float = 0.02,
-         verbose: bool = False) -> Choice:
-    """Measure every candidate on (X, y) and return the fastest."""
+         verbose: bool = False, results: list | None = None) -> Choice:
+    """Measure every candidate on (X, y) and return the fastest (every
+    measured candidate is appended to `results` when given)."""
     best = None
     for s in s_grid:
         if s * b > 4096:
@@ -84,6 +88,8 @@ def tune(X, y, b: int, eta: float = 0.5, lam: float = 1e-5, seed: int = 0,
                         print(f"s={s} mode={em}/{var} grid={gb}: {e}")
                     continue
                 ups = s / t   # SGD updates (mini-batches) per second
+                if results is not None:
+                    results.append(Choice(s, em, var, gb, ups))
                 if verbose:
                     print(f"s={s} mode={em}/{var} grid={gb}: {ups:.0f} updates/s")
                 if best is None or ups > best.updates_per_s:
