@@ -104,11 +104,12 @@ typedef struct {
      * 0 = automatic (FP64 when s*b >= 512, else FP32), 32 = FP32, 64 = FP64. */
     int32_t recur_prec;
     /* 0 = automatic (fused), 1 = one fused persistent launch for the whole
-     * fit, 2 = one launch per phase, stream ordered. With s*b > 256 and b =
-     * 16, 32, 64 or 128 both run the recurrence on one chain workgroup plus
-     * helper workgroups that add the older column blocks (fused variant 3);
-     * otherwise on one workgroup. Forms that sum the recurrence in different
-     * orders agree to rounding; each is bitwise reproducible. */
+     * fit, 2 = one launch per phase, stream ordered. With b = 16, 32, 64 or
+     * 128 the recurrence runs on one chain workgroup plus helper workgroups
+     * that add the older column blocks (stream ordered always; fused from
+     * s = 4 on, as fused variant 3); otherwise on one workgroup. Forms that
+     * sum the recurrence in different orders agree to rounding; each is
+     * bitwise reproducible. */
     int32_t exec_mode;
     /* Snapshots: when > 0, after every `snapshot_every` outer iterations the
      * current x is copied to x_history (device, FP32, row k = snapshot k,

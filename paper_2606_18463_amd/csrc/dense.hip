@@ -325,10 +325,14 @@ casgd_status plan_fit(const Dense& P, int dtype, const casgd_opts* o, int64_t H,
     plan->spin = (o && o->spin_limit > 0) ? (unsigned long long)o->spin_limit : (1ull << 24);
     // Strict block-lower Gram bytes read by each recurrence.
     const double gl_bytes = 4.0 * P.b * (double)P.b * P.s * (P.s - 1) / 2.0;
+    // Automatic variant (measured on MI355X over b = 16 .. 128, s = 2 .. 32):
+    // the multi-workgroup recurrence from s = 4 on, one recurrence workgroup
+    // beside the Gram builders at s = 2 and 3, and every workgroup running
+    // the recurrence itself only for other b with a small G_L (or s = 1).
     const bool multi_ok = rec_multi_ok(P) && P.s > 1;
     int variant = (o && o->fused_variant)
                       ? o->fused_variant
-                      : (multi_ok && sb > 256 ? 3 : (gl_bytes <= 256.0 * 1024 ? 1 : 2));
+                      : (multi_ok ? (P.s >= 4 ? 3 : 2) : (gl_bytes <= 256.0 * 1024 ? 1 : 2));
     if (variant < 1 || variant > 3) {
         set_error("fused_variant must be 0, 1, 2 or 3 (got %d)", variant);
         return CASGD_EINVAL;
