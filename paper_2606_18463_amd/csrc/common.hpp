@@ -190,7 +190,8 @@ enum : int {
     FLAG_BAR_MAIN = 32,   // the grid barrier
     FLAG_BAR_SUB = 352,   // a barrier among a subset of the workgroups
     FLAG_SLICES = 672,    // update slices finished in this launch (own line)
-    FLAG_WORDS = 704
+    FLAG_GRAM_CLAIM = 704,// Gram units claimed in this outer iteration, per parity (own line)
+    FLAG_WORDS = 736
 };
 
 // Entry points without a workspace pass flags == nullptr and report nothing.

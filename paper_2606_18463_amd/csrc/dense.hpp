@@ -417,6 +417,29 @@ __device__ __forceinline__ void gram_phase(const Dense& P, float* Gout, uint64_t
     }
 }
 
+// The Gram work of one outer iteration with dynamic shares (no K split):
+// every workgroup that reaches it claims whole units from the counter `ctr`
+// until none is left, so workgroups that join late (the recurrence
+// workgroups, once their chain is done) take what remains. Each unit is
+// computed whole by its workgroup: the result does not depend on who
+// computed what. `lds` holds kGramLds bytes.
+template <int DT>
+__device__ __forceinline__ void gram_claim(const Dense& P, float* Gout, uint64_t h, unsigned* ctr,
+                                           unsigned char* lds) {
+    __shared__ unsigned s_unit;
+    const unsigned total = (unsigned)(P.gna == 4 ? P.gt : 2 * P.gt);
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0)
+            s_unit = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const unsigned u = s_unit;
+        if (u >= total) break;
+        if (P.gna == 4) gram_unit<DT, 4>(P, Gout, h, (int)u, 0, lds);
+        else gram_unit<DT, 2>(P, Gout, h, (int)u, 0, lds);
+    }
+}
+
 // ------------------------------------------------------ update and margin
 // Column slice `slice` (slice_width<DT>() columns): optionally
 //   x <- beta^s x + alpha * sum_t c_t * scale_t * Y_t[slice]      (outer h)

@@ -65,7 +65,8 @@ __host__ __device__ inline size_t fit_lds_bytes(int sb, int s, int acc_bytes, in
 // grid, or one group of a batched launch), with the group's own barrier.
 // Per outer iteration h:
 //  * variant 3 (MULTI): phase A, workgroups 0 .. R run the multi-workgroup
-//    recurrence of h while the others build the Gram of h+1; barrier;
+//    recurrence of h while the others build the Gram of h+1 (claiming units,
+//    which the recurrence workgroups join when done); barrier;
 //    phase B, the column-slice workgroups apply the update of h fused with
 //    the partial margins of h+1, the others gather the rows of h+2 and then
 //    reduce those margins once every slice has counted in; barrier.
@@ -129,17 +130,28 @@ __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigne
                     if (!barrier_at(P.flags, FLAG_BAR_SUB, wg, nrec, spin)) return;
                 }
             }
+            // With more Gram units than Gram workgroups (and no K split) the
+            // units are claimed dynamically, and the recurrence workgroups join
+            // once their chain is done; one round of units is dealt statically.
+            const int units = P.gna == 4 ? P.gt : 2 * P.gt;
+            const bool claim = P.ksplit == 1 && units > nb - nrec;
             if (wg < nrec) {
                 rec_multi_rank<ACC>(P, pick2(P.G, cur), P.r, pick3(P.yI, slot_of(h)), P.c, spin, lds,
                                     wg);
                 if (wg == 0) phase_mark(P, hh, 1);
-            } else if (has_gram && more) {
+            } else if (has_gram && more && !claim) {
                 gram_phase<DT>(P, pick2(P.G, nxt), h + 1, base + nrec, base + nb, lds);
             }
+            if (has_gram && more && claim)
+                gram_claim<DT>(P, pick2(P.G, nxt), h + 1, P.flags + FLAG_GRAM_CLAIM + (hh & 1), lds);
             if (wg == nrec) phase_mark(P, hh, 2);
             if (wg == nb - 1) phase_mark(P, hh, 6);
             if (!grid_barrier(P.flags, wg, nb, spin)) return;
             if (wg == 0) phase_mark(P, hh, 3);
+            // every claim of this outer iteration is done: reset the counter of
+            // this parity, next used two outer iterations on
+            if (wg == 0 && threadIdx.x == 0)
+                atomic_store_relaxed(P.flags + FLAG_GRAM_CLAIM + (hh & 1), 0u);
             // Phase B: update of h fused with the margins of h+1 on the
             // column slices; workgroups without a slice gather the rows of h+2.
             // With more workgroups than slices, the ones without a slice gather
