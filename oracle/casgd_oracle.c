@@ -14,8 +14,10 @@
  *
  * Definitions followed (paper = "Mixed-Precision Communication-Avoiding SGD
  * for Generalized Linear Models on GPUs"):
- *  - empirical risk and logistic loss L(r,y) = log(1+exp(-y r)): Sec. 2.1;
- *  - residual delta = -dL/dr = y (1 - sigma(y r)): Sec. 3.1;
+ *  - empirical risk and the three losses of Sec. 2.1: logistic
+ *    L(r,y) = log(1+exp(-y r)), linear L = (r-y)^2/2, Poisson L = exp(r) - y r;
+ *  - residuals delta = -dL/dr (Sec. 3.1): y (1 - sigma(y r)), y - r and
+ *    y - exp(r);
  *  - mini-batch SGD step in delta form x <- x + (eta/b) Y^T delta: Sec. 3.1
  *    and Sec. 2.1; with the L2 term (lambda/2)||x||^2 (not in the paper) the
  *    step becomes x <- (1 - eta*lambda) x + (eta/b) Y^T delta;
@@ -74,13 +76,24 @@ void oracle_sample_indices(uint64_t seed, uint64_t t0, int64_t count, int64_t m,
 
 /* ------------------------------------------------------------- loss pieces */
 
-/* delta(z, y) = y / (1 + exp(y z)); equals y (1 - sigma(y z)). */
-static double logistic_delta(double z, double y)
+/* Loss selector: 0 logistic, 1 linear (least squares), 2 Poisson (Sec. 2.1). */
+enum { LOSS_LOGISTIC = 0, LOSS_LINEAR = 1, LOSS_POISSON = 2 };
+
+/* delta(z, y) = -dL/dz (Sec. 3.1). Logistic: y / (1 + exp(y z)), which equals
+ * y (1 - sigma(y z)); linear: y - z; Poisson: y - exp(z). */
+static double glm_delta(double z, double y, int loss)
 {
+    if (loss == LOSS_LINEAR)
+        return y - z;
+    if (loss == LOSS_POISSON)
+        return y - exp(z);
     return y / (1.0 + exp(y * z));
 }
 
+static double logistic_delta(double z, double y) { return glm_delta(z, y, LOSS_LOGISTIC); }
+
 double oracle_delta(double z, double y) { return logistic_delta(z, y); }
+double oracle_delta_glm(double z, double y, int32_t loss) { return glm_delta(z, y, loss); }
 
 /* softplus(v) = log(1 + exp(v)), evaluated without overflow. */
 static double softplus(double v)
@@ -88,9 +101,19 @@ static double softplus(double v)
     return (v > 0 ? v : 0.0) + log1p(exp(-fabs(v)));
 }
 
-/* Mean logistic loss m^-1 sum log(1 + exp(-y_i a_i^T x)) over dense rows. */
-double oracle_logloss(const double *X, int64_t ld, int64_t m, int64_t n,
-                      const double *y, const double *x)
+/* L(z, y) of Sec. 2.1; the logistic form through the stable softplus. */
+static double glm_loss(double z, double y, int loss)
+{
+    if (loss == LOSS_LINEAR)
+        return 0.5 * (z - y) * (z - y);
+    if (loss == LOSS_POISSON)
+        return exp(z) - y * z;
+    return softplus(-y * z);
+}
+
+/* Mean loss m^-1 sum L(a_i^T x, y_i) over dense rows. */
+static double mean_loss_f64(const double *X, int64_t ld, int64_t m, int64_t n,
+                            const double *y, const double *x, int loss)
 {
     double total = 0.0;
     for (int64_t i = 0; i < m; ++i) {
@@ -98,13 +121,13 @@ double oracle_logloss(const double *X, int64_t ld, int64_t m, int64_t n,
         double z = 0.0;
         for (int64_t k = 0; k < n; ++k)
             z += a[k] * x[k];
-        total += softplus(-y[i] * z);
+        total += glm_loss(z, y[i], loss);
     }
     return m > 0 ? total / (double)m : 0.0;
 }
 
-double oracle_logloss_f32(const float *X, int64_t ld, int64_t m, int64_t n,
-                          const float *y, const double *x)
+static double mean_loss_f32(const float *X, int64_t ld, int64_t m, int64_t n,
+                            const float *y, const double *x, int loss)
 {
     double total = 0.0;
 #pragma omp parallel for reduction(+ : total) schedule(static) if (m * n > OMP_MIN_WORK)
@@ -113,23 +136,62 @@ double oracle_logloss_f32(const float *X, int64_t ld, int64_t m, int64_t n,
         double z = 0.0;
         for (int64_t k = 0; k < n; ++k)
             z += (double)a[k] * x[k];
-        total += softplus(-(double)y[i] * z);
+        total += glm_loss(z, (double)y[i], loss);
     }
     return m > 0 ? total / (double)m : 0.0;
 }
 
-double oracle_logloss_csr(const int64_t *row_ptr, const int32_t *col_idx,
-                          const double *val, int64_t m, const double *y,
-                          const double *x)
+static double mean_loss_csr(const int64_t *row_ptr, const int32_t *col_idx,
+                            const double *val, int64_t m, const double *y,
+                            const double *x, int loss)
 {
     double total = 0.0;
     for (int64_t i = 0; i < m; ++i) {
         double z = 0.0;
         for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p)
             z += val[p] * x[col_idx[p]];
-        total += softplus(-y[i] * z);
+        total += glm_loss(z, y[i], loss);
     }
     return m > 0 ? total / (double)m : 0.0;
+}
+
+/* Mean logistic loss m^-1 sum log(1 + exp(-y_i a_i^T x)) over dense rows. */
+double oracle_logloss(const double *X, int64_t ld, int64_t m, int64_t n,
+                      const double *y, const double *x)
+{
+    return mean_loss_f64(X, ld, m, n, y, x, LOSS_LOGISTIC);
+}
+
+double oracle_logloss_f32(const float *X, int64_t ld, int64_t m, int64_t n,
+                          const float *y, const double *x)
+{
+    return mean_loss_f32(X, ld, m, n, y, x, LOSS_LOGISTIC);
+}
+
+double oracle_logloss_csr(const int64_t *row_ptr, const int32_t *col_idx,
+                          const double *val, int64_t m, const double *y,
+                          const double *x)
+{
+    return mean_loss_csr(row_ptr, col_idx, val, m, y, x, LOSS_LOGISTIC);
+}
+
+double oracle_loss_glm(const double *X, int64_t ld, int64_t m, int64_t n,
+                       const double *y, const double *x, int32_t loss)
+{
+    return mean_loss_f64(X, ld, m, n, y, x, loss);
+}
+
+double oracle_loss_glm_f32(const float *X, int64_t ld, int64_t m, int64_t n,
+                           const float *y, const double *x, int32_t loss)
+{
+    return mean_loss_f32(X, ld, m, n, y, x, loss);
+}
+
+double oracle_loss_glm_csr(const int64_t *row_ptr, const int32_t *col_idx,
+                           const double *val, int64_t m, const double *y,
+                           const double *x, int32_t loss)
+{
+    return mean_loss_csr(row_ptr, col_idx, val, m, y, x, loss);
 }
 
 /* ------------------------------------------------------------- dense rows */
@@ -187,7 +249,7 @@ static void decay_plus_yt_w(const double *Y, int64_t cnt, int64_t n,
 /* Plain mini-batch SGD (steps step0 .. step0+nsteps-1), in place on x. */
 static int sgd_impl(rows_t X, int64_t m, int64_t n, const double *y,
                     const float *y32, double *x, double eta, double lambda,
-                    int32_t b, uint64_t seed, uint64_t step0, int64_t nsteps)
+                    int32_t b, uint64_t seed, uint64_t step0, int64_t nsteps, int loss)
 {
     if (m <= 0 || n <= 0 || b <= 0)
         return -1;
@@ -208,7 +270,7 @@ static int sgd_impl(rows_t X, int64_t m, int64_t n, const double *y,
         rows_times_x(Y, b, n, x, z);
         for (int32_t q = 0; q < b; ++q) {
             double yq = y ? y[idx[q]] : (double)y32[idx[q]];
-            d[q] = logistic_delta(z[q], yq);
+            d[q] = glm_delta(z[q], yq, loss);
         }
         decay_plus_yt_w(Y, b, n, d, beta, alpha, x);
     }
@@ -221,7 +283,15 @@ int oracle_sgd(const double *X, int64_t ld, int64_t m, int64_t n, const double *
                uint64_t step0, int64_t nsteps)
 {
     rows_t R = {X, 0, ld};
-    return sgd_impl(R, m, n, y, NULL, x, eta, lambda, b, seed, step0, nsteps);
+    return sgd_impl(R, m, n, y, NULL, x, eta, lambda, b, seed, step0, nsteps, LOSS_LOGISTIC);
+}
+
+int oracle_sgd_glm(const double *X, int64_t ld, int64_t m, int64_t n, const double *y,
+                   double *x, double eta, double lambda, int32_t b, uint64_t seed,
+                   uint64_t step0, int64_t nsteps, int32_t loss)
+{
+    rows_t R = {X, 0, ld};
+    return sgd_impl(R, m, n, y, NULL, x, eta, lambda, b, seed, step0, nsteps, loss);
 }
 
 int oracle_sgd_f32(const float *X, int64_t ld, int64_t m, int64_t n, const float *y,
@@ -229,7 +299,15 @@ int oracle_sgd_f32(const float *X, int64_t ld, int64_t m, int64_t n, const float
                    uint64_t step0, int64_t nsteps)
 {
     rows_t R = {X, 1, ld};
-    return sgd_impl(R, m, n, NULL, y, x, eta, lambda, b, seed, step0, nsteps);
+    return sgd_impl(R, m, n, NULL, y, x, eta, lambda, b, seed, step0, nsteps, LOSS_LOGISTIC);
+}
+
+int oracle_sgd_glm_f32(const float *X, int64_t ld, int64_t m, int64_t n, const float *y,
+                       double *x, double eta, double lambda, int32_t b, uint64_t seed,
+                       uint64_t step0, int64_t nsteps, int32_t loss)
+{
+    rows_t R = {X, 1, ld};
+    return sgd_impl(R, m, n, NULL, y, x, eta, lambda, b, seed, step0, nsteps, loss);
 }
 
 /* One s-step outer iteration's data-dependent pieces for rows Y (sb x n):
@@ -257,7 +335,7 @@ static void margin_and_gram(const double *Y, int32_t b, int32_t s, int64_t n,
  * Outputs delta[sb] and c[sb] = beta^(s-1-j) delta for rows of block j. */
 static void inner_corrections(const double *G, const double *r, const double *yI,
                               int32_t b, int32_t s, double alpha, double beta,
-                              double *delta, double *c)
+                              double *delta, double *c, int loss)
 {
     const int64_t sb = (int64_t)s * b;
     for (int32_t j = 0; j < s; ++j) {
@@ -273,7 +351,7 @@ static void inner_corrections(const double *G, const double *r, const double *yI
                 acc += w * part;
             }
             const double z = bj * r[t] + alpha * acc;
-            delta[t] = logistic_delta(z, yI[t]);
+            delta[t] = glm_delta(z, yI[t], loss);
         }
     }
     for (int32_t j = 0; j < s; ++j) {
@@ -287,7 +365,16 @@ int oracle_inner_corrections(const double *G, const double *r, const double *yI,
                              int32_t b, int32_t s, double eta, double lambda,
                              double *delta, double *c)
 {
-    inner_corrections(G, r, yI, b, s, eta / (double)b, 1.0 - eta * lambda, delta, c);
+    inner_corrections(G, r, yI, b, s, eta / (double)b, 1.0 - eta * lambda, delta, c,
+                      LOSS_LOGISTIC);
+    return 0;
+}
+
+int oracle_inner_corrections_glm(const double *G, const double *r, const double *yI,
+                                 int32_t b, int32_t s, double eta, double lambda,
+                                 double *delta, double *c, int32_t loss)
+{
+    inner_corrections(G, r, yI, b, s, eta / (double)b, 1.0 - eta * lambda, delta, c, loss);
     return 0;
 }
 
@@ -317,7 +404,7 @@ static void ws_free(outer_ws *w)
 static int casgd_impl(rows_t X, int64_t m, int64_t n, const double *y,
                       const float *y32, double *x, double eta, double lambda,
                       int32_t b, int32_t s, uint64_t seed, uint64_t outer0,
-                      int64_t nouter)
+                      int64_t nouter, int loss)
 {
     if (m <= 0 || n <= 0 || b <= 0 || s <= 0)
         return -1;
@@ -337,7 +424,7 @@ static int casgd_impl(rows_t X, int64_t m, int64_t n, const double *y,
         for (int64_t q = 0; q < sb; ++q)
             w.yI[q] = y ? y[w.idx[q]] : (double)y32[w.idx[q]];
         margin_and_gram(w.Y, b, s, n, x, w.r, w.G);
-        inner_corrections(w.G, w.r, w.yI, b, s, alpha, beta, w.delta, w.c);
+        inner_corrections(w.G, w.r, w.yI, b, s, alpha, beta, w.delta, w.c, loss);
         decay_plus_yt_w(w.Y, sb, n, w.c, beta_s, alpha, x);
     }
     ws_free(&w);
@@ -349,7 +436,16 @@ int oracle_casgd(const double *X, int64_t ld, int64_t m, int64_t n, const double
                  uint64_t seed, uint64_t outer0, int64_t nouter)
 {
     rows_t R = {X, 0, ld};
-    return casgd_impl(R, m, n, y, NULL, x, eta, lambda, b, s, seed, outer0, nouter);
+    return casgd_impl(R, m, n, y, NULL, x, eta, lambda, b, s, seed, outer0, nouter,
+                      LOSS_LOGISTIC);
+}
+
+int oracle_casgd_glm(const double *X, int64_t ld, int64_t m, int64_t n, const double *y,
+                     double *x, double eta, double lambda, int32_t b, int32_t s,
+                     uint64_t seed, uint64_t outer0, int64_t nouter, int32_t loss)
+{
+    rows_t R = {X, 0, ld};
+    return casgd_impl(R, m, n, y, NULL, x, eta, lambda, b, s, seed, outer0, nouter, loss);
 }
 
 int oracle_casgd_f32(const float *X, int64_t ld, int64_t m, int64_t n,
@@ -358,17 +454,27 @@ int oracle_casgd_f32(const float *X, int64_t ld, int64_t m, int64_t n,
                      int64_t nouter)
 {
     rows_t R = {X, 1, ld};
-    return casgd_impl(R, m, n, NULL, y, x, eta, lambda, b, s, seed, outer0, nouter);
+    return casgd_impl(R, m, n, NULL, y, x, eta, lambda, b, s, seed, outer0, nouter,
+                      LOSS_LOGISTIC);
+}
+
+int oracle_casgd_glm_f32(const float *X, int64_t ld, int64_t m, int64_t n,
+                         const float *y, double *x, double eta, double lambda,
+                         int32_t b, int32_t s, uint64_t seed, uint64_t outer0,
+                         int64_t nouter, int32_t loss)
+{
+    rows_t R = {X, 1, ld};
+    return casgd_impl(R, m, n, NULL, y, x, eta, lambda, b, s, seed, outer0, nouter, loss);
 }
 
 /* The pieces of outer iteration `outer` from the current x, for per-step
  * comparisons: sampled indices, labels, r, strict block-lower G, and the
  * recurrence outputs delta and c. x is not modified. */
-int oracle_outer_parts(const double *X, int64_t ld, int64_t m, int64_t n,
-                       const double *y, const double *x, double eta, double lambda,
-                       int32_t b, int32_t s, uint64_t seed, uint64_t outer,
-                       int64_t *idx_out, double *yI_out, double *r_out,
-                       double *G_out, double *delta_out, double *c_out)
+int oracle_outer_parts_glm(const double *X, int64_t ld, int64_t m, int64_t n,
+                           const double *y, const double *x, double eta, double lambda,
+                           int32_t b, int32_t s, uint64_t seed, uint64_t outer,
+                           int64_t *idx_out, double *yI_out, double *r_out,
+                           double *G_out, double *delta_out, double *c_out, int32_t loss)
 {
     if (m <= 0 || n <= 0 || b <= 0 || s <= 0)
         return -1;
@@ -383,9 +489,19 @@ int oracle_outer_parts(const double *X, int64_t ld, int64_t m, int64_t n,
         yI_out[q] = y[idx_out[q]];
     margin_and_gram(Y, b, s, n, x, r_out, G_out);
     inner_corrections(G_out, r_out, yI_out, b, s, eta / (double)b, 1.0 - eta * lambda,
-                      delta_out, c_out);
+                      delta_out, c_out, loss);
     free(Y);
     return 0;
+}
+
+int oracle_outer_parts(const double *X, int64_t ld, int64_t m, int64_t n,
+                       const double *y, const double *x, double eta, double lambda,
+                       int32_t b, int32_t s, uint64_t seed, uint64_t outer,
+                       int64_t *idx_out, double *yI_out, double *r_out,
+                       double *G_out, double *delta_out, double *c_out)
+{
+    return oracle_outer_parts_glm(X, ld, m, n, y, x, eta, lambda, b, s, seed, outer, idx_out,
+                                  yI_out, r_out, G_out, delta_out, c_out, LOSS_LOGISTIC);
 }
 
 /* ------------------------------------------------------------- CSR rows */
@@ -412,10 +528,10 @@ static double sparse_dot(const int32_t *ca, const double *va, int64_t na,
 /* s-step SGD on a CSR matrix (column indices sorted within each row). Same
  * arithmetic as the dense version with the zero entries skipped; the sums
  * visit the stored entries in column order. */
-int oracle_casgd_csr(const int64_t *row_ptr, const int32_t *col_idx, const double *val,
-                     int64_t m, int64_t n, const double *y, double *x, double eta,
-                     double lambda, int32_t b, int32_t s, uint64_t seed,
-                     uint64_t outer0, int64_t nouter)
+int oracle_casgd_csr_glm(const int64_t *row_ptr, const int32_t *col_idx, const double *val,
+                         int64_t m, int64_t n, const double *y, double *x, double eta,
+                         double lambda, int32_t b, int32_t s, uint64_t seed,
+                         uint64_t outer0, int64_t nouter, int32_t loss)
 {
     if (m <= 0 || n <= 0 || b <= 0 || s <= 0)
         return -1;
@@ -457,7 +573,7 @@ int oracle_casgd_csr(const int64_t *row_ptr, const int32_t *col_idx, const doubl
                                            row_ptr[iu + 1] - row_ptr[iu]);
             }
         }
-        inner_corrections(G, r, yI, b, s, alpha, beta, d, c);
+        inner_corrections(G, r, yI, b, s, alpha, beta, d, c, loss);
         /* x <- beta^s x + alpha * Y^T c: accumulate Y^T c column by column in
          * sample order, then apply. */
         memset(g, 0, sizeof(double) * (size_t)n);
@@ -471,6 +587,15 @@ int oracle_casgd_csr(const int64_t *row_ptr, const int32_t *col_idx, const doubl
     }
     free(idx); free(r); free(G); free(yI); free(d); free(c); free(g);
     return 0;
+}
+
+int oracle_casgd_csr(const int64_t *row_ptr, const int32_t *col_idx, const double *val,
+                     int64_t m, int64_t n, const double *y, double *x, double eta,
+                     double lambda, int32_t b, int32_t s, uint64_t seed,
+                     uint64_t outer0, int64_t nouter)
+{
+    return oracle_casgd_csr_glm(row_ptr, col_idx, val, m, n, y, x, eta, lambda, b, s, seed,
+                                outer0, nouter, LOSS_LOGISTIC);
 }
 
 int oracle_num_threads(void)

@@ -1,4 +1,6 @@
-"""FP64 CPU oracle for s-step mini-batch SGD on L2-regularised logistic regression.
+"""FP64 CPU oracle for s-step mini-batch SGD on L2-regularised generalized linear
+models: logistic regression (the default), linear regression and Poisson
+regression (the three losses of Sec. 2.1, residuals of Sec. 3.1).
 
 TEST INFRASTRUCTURE ONLY: only the tests, the smoke check and the CPU-baseline
 leg of the benchmark may import this module. It shares no code with the GPU
@@ -8,8 +10,8 @@ from it.
 Two layers:
 
 * the C core (``casgd_oracle.c`` -> ``liboracle.so``): plain mini-batch SGD,
-  the s-step outer iteration, its pieces, a CSR variant and the logistic
-  loss, all in IEEE double with left-to-right sums;
+  the s-step outer iteration, its pieces, a CSR variant and the losses, for
+  each of the three losses, all in IEEE double with left-to-right sums;
 * NumPy FP64 code here: a second, independent pure-Python SGD for tiny
   cases, the storage formats (BF16, FP16, OCP FP8-e4m3 with per-row scales)
   written from their definitions, the local error bound of the paper's
@@ -85,6 +87,36 @@ def lib():
         L.oracle_casgd_csr.restype = ctypes.c_int
         L.oracle_casgd_csr.argtypes = [_pi64, _pi32, _pd, _i64, _i64, _pd, _pd, _dbl,
                                        _dbl, _i32, _i32, _u64, _u64, _i64]
+        L.oracle_delta_glm.restype = _dbl
+        L.oracle_delta_glm.argtypes = [_dbl, _dbl, _i32]
+        L.oracle_loss_glm.restype = _dbl
+        L.oracle_loss_glm.argtypes = [_pd, _i64, _i64, _i64, _pd, _pd, _i32]
+        L.oracle_loss_glm_f32.restype = _dbl
+        L.oracle_loss_glm_f32.argtypes = [_pf, _i64, _i64, _i64, _pf, _pd, _i32]
+        L.oracle_loss_glm_csr.restype = _dbl
+        L.oracle_loss_glm_csr.argtypes = [_pi64, _pi32, _pd, _i64, _pd, _pd, _i32]
+        L.oracle_sgd_glm.restype = ctypes.c_int
+        L.oracle_sgd_glm.argtypes = [_pd, _i64, _i64, _i64, _pd, _pd, _dbl, _dbl, _i32,
+                                     _u64, _u64, _i64, _i32]
+        L.oracle_sgd_glm_f32.restype = ctypes.c_int
+        L.oracle_sgd_glm_f32.argtypes = [_pf, _i64, _i64, _i64, _pf, _pd, _dbl, _dbl, _i32,
+                                         _u64, _u64, _i64, _i32]
+        L.oracle_casgd_glm.restype = ctypes.c_int
+        L.oracle_casgd_glm.argtypes = [_pd, _i64, _i64, _i64, _pd, _pd, _dbl, _dbl, _i32,
+                                       _i32, _u64, _u64, _i64, _i32]
+        L.oracle_casgd_glm_f32.restype = ctypes.c_int
+        L.oracle_casgd_glm_f32.argtypes = [_pf, _i64, _i64, _i64, _pf, _pd, _dbl, _dbl,
+                                           _i32, _i32, _u64, _u64, _i64, _i32]
+        L.oracle_outer_parts_glm.restype = ctypes.c_int
+        L.oracle_outer_parts_glm.argtypes = [_pd, _i64, _i64, _i64, _pd, _pd, _dbl, _dbl,
+                                             _i32, _i32, _u64, _u64, _pi64, _pd, _pd, _pd,
+                                             _pd, _pd, _i32]
+        L.oracle_inner_corrections_glm.restype = ctypes.c_int
+        L.oracle_inner_corrections_glm.argtypes = [_pd, _pd, _pd, _i32, _i32, _dbl, _dbl,
+                                                   _pd, _pd, _i32]
+        L.oracle_casgd_csr_glm.restype = ctypes.c_int
+        L.oracle_casgd_csr_glm.argtypes = [_pi64, _pi32, _pd, _i64, _i64, _pd, _pd, _dbl,
+                                           _dbl, _i32, _i32, _u64, _u64, _i64, _i32]
         L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_num_threads.argtypes = []
         _lib = L
@@ -102,6 +134,15 @@ def _f64(a) -> np.ndarray:
 def _check(rc: int) -> None:
     if rc != 0:
         raise RuntimeError(f"oracle call failed with code {rc}")
+
+
+# Loss selector of the C core (Sec. 2.1): logistic, linear (least squares),
+# Poisson.
+LOSSES = {"logistic": 0, "linear": 1, "poisson": 2}
+
+
+def _loss_code(loss) -> int:
+    return LOSSES[loss] if isinstance(loss, str) else int(loss)
 
 
 # ------------------------------------------------------------------ sampling
@@ -132,41 +173,43 @@ def _rows(X: np.ndarray):
 
 
 def sgd(X, y, x0, eta: float, lam: float, b: int, seed: int, step0: int = 0,
-        nsteps: int = 1) -> np.ndarray:
+        nsteps: int = 1, loss="logistic") -> np.ndarray:
     """Plain mini-batch SGD in delta form with L2 decay (Sec. 3.1)."""
     Xr, f32 = _rows(X)
     x = _f64(x0).copy()
     m, n = Xr.shape
+    lc = _loss_code(loss)
     if f32:
         yv = np.ascontiguousarray(y, dtype=np.float32)
-        _check(lib().oracle_sgd_f32(_p(Xr, _pf), n, m, n, _p(yv, _pf), _p(x, _pd),
-                                    eta, lam, b, seed, step0, nsteps))
+        _check(lib().oracle_sgd_glm_f32(_p(Xr, _pf), n, m, n, _p(yv, _pf), _p(x, _pd),
+                                        eta, lam, b, seed, step0, nsteps, lc))
     else:
         yv = _f64(y)
-        _check(lib().oracle_sgd(_p(Xr, _pd), n, m, n, _p(yv, _pd), _p(x, _pd),
-                                eta, lam, b, seed, step0, nsteps))
+        _check(lib().oracle_sgd_glm(_p(Xr, _pd), n, m, n, _p(yv, _pd), _p(x, _pd),
+                                    eta, lam, b, seed, step0, nsteps, lc))
     return x
 
 
 def casgd(X, y, x0, eta: float, lam: float, b: int, s: int, seed: int,
-          outer0: int = 0, nouter: int = 1) -> np.ndarray:
+          outer0: int = 0, nouter: int = 1, loss="logistic") -> np.ndarray:
     """s-step SGD (Algorithm 1 with L2 decay), ``nouter`` outer iterations."""
     Xr, f32 = _rows(X)
     x = _f64(x0).copy()
     m, n = Xr.shape
+    lc = _loss_code(loss)
     if f32:
         yv = np.ascontiguousarray(y, dtype=np.float32)
-        _check(lib().oracle_casgd_f32(_p(Xr, _pf), n, m, n, _p(yv, _pf), _p(x, _pd),
-                                      eta, lam, b, s, seed, outer0, nouter))
+        _check(lib().oracle_casgd_glm_f32(_p(Xr, _pf), n, m, n, _p(yv, _pf), _p(x, _pd),
+                                          eta, lam, b, s, seed, outer0, nouter, lc))
     else:
         yv = _f64(y)
-        _check(lib().oracle_casgd(_p(Xr, _pd), n, m, n, _p(yv, _pd), _p(x, _pd),
-                                  eta, lam, b, s, seed, outer0, nouter))
+        _check(lib().oracle_casgd_glm(_p(Xr, _pd), n, m, n, _p(yv, _pd), _p(x, _pd),
+                                      eta, lam, b, s, seed, outer0, nouter, lc))
     return x
 
 
 def outer_parts(X, y, x, eta: float, lam: float, b: int, s: int, seed: int,
-                outer: int) -> dict:
+                outer: int, loss="logistic") -> dict:
     """idx, yI, r, strict block-lower G, delta and c of one outer iteration."""
     Xr = _f64(X)
     yv = _f64(y)
@@ -179,25 +222,50 @@ def outer_parts(X, y, x, eta: float, lam: float, b: int, s: int, seed: int,
     G = np.empty((sb, sb))
     d = np.empty(sb)
     c = np.empty(sb)
-    _check(lib().oracle_outer_parts(_p(Xr, _pd), n, m, n, _p(yv, _pd), _p(xv, _pd),
-                                    eta, lam, b, s, seed, outer, _p(idx, _pi64),
-                                    _p(yI, _pd), _p(r, _pd), _p(G, _pd), _p(d, _pd),
-                                    _p(c, _pd)))
+    _check(lib().oracle_outer_parts_glm(_p(Xr, _pd), n, m, n, _p(yv, _pd), _p(xv, _pd),
+                                        eta, lam, b, s, seed, outer, _p(idx, _pi64),
+                                        _p(yI, _pd), _p(r, _pd), _p(G, _pd), _p(d, _pd),
+                                        _p(c, _pd), _loss_code(loss)))
     return dict(idx=idx, yI=yI, r=r, G=G, delta=d, c=c)
 
 
-def inner_corrections(G, r, yI, b: int, s: int, eta: float, lam: float):
+def inner_corrections(G, r, yI, b: int, s: int, eta: float, lam: float, loss="logistic"):
     """The s residual corrections of Algorithm 1 (with decay): (delta, c)."""
     Gv, rv, yv = _f64(G), _f64(r), _f64(yI)
     d = np.empty(s * b)
     c = np.empty(s * b)
-    _check(lib().oracle_inner_corrections(_p(Gv, _pd), _p(rv, _pd), _p(yv, _pd), b, s,
-                                          eta, lam, _p(d, _pd), _p(c, _pd)))
+    _check(lib().oracle_inner_corrections_glm(_p(Gv, _pd), _p(rv, _pd), _p(yv, _pd), b, s,
+                                              eta, lam, _p(d, _pd), _p(c, _pd),
+                                              _loss_code(loss)))
     return d, c
 
 
-def delta(z: float, y: float) -> float:
-    return float(lib().oracle_delta(z, y))
+def delta(z: float, y: float, loss="logistic") -> float:
+    """Residual -dL/dz of Sec. 3.1 for one sample."""
+    return float(lib().oracle_delta_glm(z, y, _loss_code(loss)))
+
+
+def loss_value(X, y, x, loss="logistic") -> float:
+    """Mean loss m^-1 sum L(a_i^T x, y_i) of Sec. 2.1 (unregularised)."""
+    xv = _f64(x)
+    lc = _loss_code(loss)
+    if X.dtype == np.float32:
+        Xr = np.ascontiguousarray(X)
+        yv = np.ascontiguousarray(y, dtype=np.float32)
+        return float(lib().oracle_loss_glm_f32(_p(Xr, _pf), Xr.shape[1], Xr.shape[0],
+                                               Xr.shape[1], _p(yv, _pf), _p(xv, _pd), lc))
+    Xr, yv = _f64(X), _f64(y)
+    return float(lib().oracle_loss_glm(_p(Xr, _pd), Xr.shape[1], Xr.shape[0], Xr.shape[1],
+                                       _p(yv, _pd), _p(xv, _pd), lc))
+
+
+def loss_value_csr(row_ptr, col_idx, values, y, x, loss="logistic") -> float:
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    va, yv, xv = _f64(values), _f64(y), _f64(x)
+    return float(lib().oracle_loss_glm_csr(_p(rp, _pi64), _p(ci, _pi32), _p(va, _pd),
+                                           rp.shape[0] - 1, _p(yv, _pd), _p(xv, _pd),
+                                           _loss_code(loss)))
 
 
 def logloss(X, y, x) -> float:
@@ -220,15 +288,16 @@ def objective(X, y, x, lam: float) -> float:
 
 
 def casgd_csr(row_ptr, col_idx, values, n: int, y, x0, eta: float, lam: float,
-              b: int, s: int, seed: int, outer0: int = 0, nouter: int = 1) -> np.ndarray:
+              b: int, s: int, seed: int, outer0: int = 0, nouter: int = 1,
+              loss="logistic") -> np.ndarray:
     rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
     ci = np.ascontiguousarray(col_idx, dtype=np.int32)
     va = _f64(values)
     yv = _f64(y)
     x = _f64(x0).copy()
-    _check(lib().oracle_casgd_csr(_p(rp, _pi64), _p(ci, _pi32), _p(va, _pd),
-                                  rp.shape[0] - 1, n, _p(yv, _pd), _p(x, _pd), eta, lam,
-                                  b, s, seed, outer0, nouter))
+    _check(lib().oracle_casgd_csr_glm(_p(rp, _pi64), _p(ci, _pi32), _p(va, _pd),
+                                      rp.shape[0] - 1, n, _p(yv, _pd), _p(x, _pd), eta, lam,
+                                      b, s, seed, outer0, nouter, _loss_code(loss)))
     return x
 
 
@@ -257,7 +326,7 @@ def py_sample_indices(seed: int, t0: int, count: int, m: int) -> np.ndarray:
                     dtype=np.int64)
 
 
-def py_sgd(X, y, x0, eta, lam, b, seed, nsteps):
+def py_sgd(X, y, x0, eta, lam, b, seed, nsteps, loss="logistic"):
     """Second implementation of plain SGD with NumPy vector ops (tiny inputs).
 
     Independent of the C core: it recomputes the samples, the residual and the
@@ -267,12 +336,18 @@ def py_sgd(X, y, x0, eta, lam, b, seed, nsteps):
     y = _f64(y)
     x = _f64(x0).copy()
     m = X.shape[0]
+    lc = _loss_code(loss)
     for k in range(nsteps):
         I = py_sample_indices(seed, k * b, b, m)
         Y = X[I]
         z = Y @ x
         yi = y[I]
-        dlt = yi * (1.0 - 1.0 / (1.0 + np.exp(-yi * z)))   # y (1 - sigma(y z))
+        if lc == 1:
+            dlt = yi - z                                         # linear
+        elif lc == 2:
+            dlt = yi - np.exp(z)                                 # Poisson
+        else:
+            dlt = yi * (1.0 - 1.0 / (1.0 + np.exp(-yi * z)))     # y (1 - sigma(y z))
         x = (1.0 - eta * lam) * x + (eta / b) * (Y.T @ dlt)
     return x
 

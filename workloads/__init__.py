@@ -11,10 +11,13 @@ from .generators import (  # noqa: F401
     SparseProblem,
     dense_c1,
     dense_c2,
+    dense_glm,
     dense_logreg,
+    glm_labels,
     lambda_path_c4,
     normalize_rows,
     sparse_c4,
+    sparse_zipf_glm,
     sparse_zipf_logreg,
     uneven_problem_specs,
     uneven_problem,

@@ -21,7 +21,14 @@ Workloads (the paper's datasets are not available; these stand in for them):
   spread S log-uniform in [1, 1e3], column scales log-uniform in [1, S],
   entries N(0, 1/n) * scale.
 
-``sign(0)`` is +1 throughout. Labels are stored as float32 +-1.
+* ``dense_glm`` / ``sparse_zipf_glm`` -- the same feature matrices with
+  labels for the linear and Poisson losses: linear y = Xw + eps with
+  eps ~ N(0, noise_var); Poisson y ~ Poisson(exp(rate_scale * Xw)), counts
+  (the paper's Poisson-synth generator is not specified; rate_scale = 0.5
+  keeps the rates near exp(+-1) for unit-variance margins).
+
+``sign(0)`` is +1 throughout. Logistic labels are stored as float32 +-1,
+linear and Poisson labels as float32 values.
 """
 from __future__ import annotations
 
@@ -278,6 +285,55 @@ def sparse_zipf_logreg(m: int, n: int, seed: int, *, nnz_mean: float = 50.0,
     meta = dict(m=m, n=n, seed=seed, nnz_mean=nnz_mean, zipf_a=zipf_a,
                 noise_var=noise_var)
     return SparseProblem(rp, ci, va, n, y, trp, tci, tva, yt, w, meta)
+
+
+def glm_labels(margin: np.ndarray, loss: str, seq, *, noise_var: float = 0.1,
+               rate_scale: float = 0.5) -> np.ndarray:
+    """Labels for planted margins (data generation only): logistic
+    sign(margin + eps), linear margin + eps, Poisson draws with mean
+    exp(rate_scale * margin); eps ~ N(0, noise_var)."""
+    if loss == "logistic":
+        return _labels(margin, seq, noise_var, None, 0.0)
+    g = np.random.Generator(np.random.PCG64(seq))
+    if loss == "linear":
+        return (margin + g.standard_normal(margin.shape[0]) * math.sqrt(noise_var)).astype(
+            np.float32)
+    if loss == "poisson":
+        return g.poisson(np.exp(rate_scale * margin)).astype(np.float32)
+    raise ValueError(loss)
+
+
+def dense_glm(m: int, n: int, seed: int, loss: str, *, var: float, noise_var: float = 0.1,
+              rate_scale: float = 0.5, m_test: int | None = None,
+              dtype=np.float64) -> DenseProblem:
+    """Dense planted-w data with labels for `loss` (see glm_labels)."""
+    p = dense_logreg(m, n, seed, var=var, m_test=m_test, dtype=dtype)
+    s_y, s_yt = np.random.SeedSequence([seed, 11]).spawn(2)
+    p.y = glm_labels(_margins(p.X, p.w_true), loss, s_y, noise_var=noise_var,
+                     rate_scale=rate_scale)
+    p.y_test = glm_labels(_margins(p.X_test, p.w_true), loss, s_yt, noise_var=noise_var,
+                          rate_scale=rate_scale)
+    p.meta.update(loss=loss, noise_var=noise_var, rate_scale=rate_scale)
+    return p
+
+
+def sparse_zipf_glm(m: int, n: int, seed: int, loss: str, *, nnz_mean: float = 50.0,
+                    noise_var: float = 0.1, rate_scale: float = 0.5) -> SparseProblem:
+    """The Zipf CSR matrix of sparse_zipf_logreg with labels for `loss`."""
+    p = sparse_zipf_logreg(m, n, seed, nnz_mean=nnz_mean, noise_var=noise_var)
+    s_y, s_yt = np.random.SeedSequence([seed, 13]).spawn(2)
+
+    def margin(rp, ci, va):
+        mm = rp.shape[0] - 1
+        rows = np.repeat(np.arange(mm), np.diff(rp))
+        return np.bincount(rows, weights=va.astype(np.float64) * p.w_true[ci], minlength=mm)
+
+    p.y = glm_labels(margin(p.row_ptr, p.col_idx, p.values), loss, s_y,
+                     noise_var=noise_var, rate_scale=rate_scale)
+    p.y_test = glm_labels(margin(p.test_row_ptr, p.test_col_idx, p.test_values), loss, s_yt,
+                          noise_var=noise_var, rate_scale=rate_scale)
+    p.meta.update(loss=loss, rate_scale=rate_scale)
+    return p
 
 
 def sparse_c4(seed: int = 42, m: int = 1_000_000, n: int = 1 << 17) -> SparseProblem:
