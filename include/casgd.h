@@ -1,6 +1,7 @@
 /*
  * casgd.h -- C ABI of libcasgd: s-step (communication-avoiding) mini-batch SGD
- * for L2-regularised logistic regression on AMD Instinct MI355X (gfx950).
+ * for L2-regularised logistic regression (and the linear and Poisson models
+ * of the same paper) on AMD Instinct MI355X (gfx950).
  *
  * Method: "Mixed-Precision Communication-Avoiding SGD for Generalized Linear
  * Models on GPUs". One outer iteration (Algorithm 1) samples s blocks of b
@@ -72,6 +73,15 @@ enum {
     CASGD_F16 = 2,      /* IEEE binary16 */
     CASGD_FP8E4M3 = 3   /* OCP FP8 E4M3 (bias 7, max 448, no Inf); needs row_scale */
 };
+
+/* Losses of the generalized linear model (Sec. 2.1) with their residuals
+ * delta = -dL/dz at the margin z = a^T x (Sec. 3.1):
+ *   LOGISTIC  L = log(1 + exp(-y z)), y in {-1, +1}   delta = y / (1 + exp(y z))
+ *   LINEAR    L = (z - y)^2 / 2, y real               delta = y - z
+ *   POISSON   L = exp(z) - y z, y >= 0 (counts)       delta = y - exp(z)
+ * Only the residual formula of the s-step recurrence and the evaluated loss
+ * depend on it; sampling, Gram, margins and update are the same kernels. */
+enum { CASGD_LOSS_LOGISTIC = 0, CASGD_LOSS_LINEAR = 1, CASGD_LOSS_POISSON = 2 };
 
 /* Matrix layouts. */
 enum { CASGD_DENSE = 0, CASGD_CSR = 1 };
@@ -150,6 +160,8 @@ typedef struct {
      * recurrence of one group of four lanes, splitting the rows of every
      * block; a power of two dividing b (0 = automatic). */
     int32_t rec_split;
+    /* CASGD_LOSS_* (0 = logistic). */
+    int32_t loss;
 } casgd_opts;
 
 const char *casgd_status_string(casgd_status st);
@@ -248,7 +260,7 @@ typedef struct {
     int32_t groups;
     int32_t variant;
     int32_t recur_prec;
-    int32_t reserved;
+    int32_t loss;        /* CASGD_LOSS_* */
 } casgd_problem;
 
 /* Bytes of the device table workspace of a batch of `count` problems. */
@@ -288,11 +300,22 @@ casgd_status casgd_gram_margin(const casgd_matrix *X, const float *x, int32_t b,
  * device inputs G (FP32 s*b x s*b row-major, strict block-lower part read),
  * r (FP32 s*b) and labels yI (FP32 s*b); writes c (device, FP32, s*b) with
  * c_t = beta^(s-1-j) delta_t for t in block j, and delta (device, FP32, s*b)
- * if not NULL. prec: 0 auto, 32, 64 as casgd_opts.recur_prec.
+ * if not NULL. prec: 0 auto, 32, 64 as casgd_opts.recur_prec; loss:
+ * CASGD_LOSS_*. form selects the execution form the fits use:
+ *   0 = automatic (2 when b is 16, 32, 64 or 128 and s > 1, else 1),
+ *   1 = one workgroup streams the whole strict block-lower part,
+ *   2 = a chain workgroup plus s - 3 helper workgroups (s - 2 for b = 128)
+ *       that add the older column blocks and exchange tagged words (the form
+ *       of the fused fit from s = 4 on); b must be 16, 32, 64 or 128.
+ * ws (device, 256-byte aligned, casgd_recurrence_workspace_size bytes) holds
+ * the exchange words and device flags; it may be NULL for form 1. Flags are
+ * reported by casgd_check(ws) as for a fit.
  */
+size_t casgd_recurrence_workspace_size(int32_t b, int32_t s);
 casgd_status casgd_recurrence(const float *G, const float *r, const float *yI, int32_t b,
-                              int32_t s, double eta, double lambda, int32_t prec,
-                              float *c, float *delta, void *stream);
+                              int32_t s, double eta, double lambda, int32_t prec, int32_t loss,
+                              int32_t form, float *c, float *delta, void *ws, size_t ws_bytes,
+                              void *stream);
 
 /* x <- beta^s x + (eta/b) Y^T c for outer iteration `outer_iter` (Algorithm 1,
  * gradient and update steps, fused). c: device FP32 s*b (row scales are
@@ -411,6 +434,13 @@ size_t casgd_logloss_workspace_size(int64_t count);
 casgd_status casgd_logloss(const casgd_matrix *X, const float *y, const float *xs,
                            int64_t count, int64_t x_stride, double *out, void *ws,
                            size_t ws_bytes, void *stream);
+
+/* Mean loss m^-1 sum_i L(a_i^T x, y_i) of any of the three losses of Sec. 2.1
+ * (loss = CASGD_LOSS_*); otherwise as casgd_logloss, with the same workspace
+ * size. The Poisson terms may overflow to +Inf for huge margins. */
+casgd_status casgd_loss(const casgd_matrix *X, const float *y, const float *xs, int64_t count,
+                        int64_t x_stride, int32_t loss, double *out, void *ws, size_t ws_bytes,
+                        void *stream);
 
 /*
  * Per-column statistics (device, FP32, n x 4 row-major): mean, population

@@ -494,6 +494,27 @@ int oracle_outer_parts_glm(const double *X, int64_t ld, int64_t m, int64_t n,
     return 0;
 }
 
+/* One outer iteration on given sampled rows Y (sb x n, row-major) with their
+ * labels yI: Algorithm 1 after the sampling and gather steps (margins, strict
+ * block-lower Gram, inner corrections, update). Writes r, G, delta, c and the
+ * new iterate x_out (n); x is not modified. */
+int oracle_outer_rows_glm(const double *Y, int64_t n, const double *yI, const double *x,
+                          double eta, double lambda, int32_t b, int32_t s,
+                          double *r_out, double *G_out, double *delta_out, double *c_out,
+                          double *x_out, int32_t loss)
+{
+    if (n <= 0 || b <= 0 || s <= 0)
+        return -1;
+    const int64_t sb = (int64_t)s * b;
+    const double alpha = eta / (double)b;
+    const double beta = 1.0 - eta * lambda;
+    margin_and_gram(Y, b, s, n, x, r_out, G_out);
+    inner_corrections(G_out, r_out, yI, b, s, alpha, beta, delta_out, c_out, loss);
+    memcpy(x_out, x, sizeof(double) * (size_t)n);
+    decay_plus_yt_w(Y, sb, n, c_out, pow(beta, (double)s), alpha, x_out);
+    return 0;
+}
+
 int oracle_outer_parts(const double *X, int64_t ld, int64_t m, int64_t n,
                        const double *y, const double *x, double eta, double lambda,
                        int32_t b, int32_t s, uint64_t seed, uint64_t outer,

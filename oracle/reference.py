@@ -111,6 +111,9 @@ def lib():
         L.oracle_outer_parts_glm.argtypes = [_pd, _i64, _i64, _i64, _pd, _pd, _dbl, _dbl,
                                              _i32, _i32, _u64, _u64, _pi64, _pd, _pd, _pd,
                                              _pd, _pd, _i32]
+        L.oracle_outer_rows_glm.restype = ctypes.c_int
+        L.oracle_outer_rows_glm.argtypes = [_pd, _i64, _pd, _pd, _dbl, _dbl, _i32, _i32, _pd,
+                                            _pd, _pd, _pd, _pd, _i32]
         L.oracle_inner_corrections_glm.restype = ctypes.c_int
         L.oracle_inner_corrections_glm.argtypes = [_pd, _pd, _pd, _i32, _i32, _dbl, _dbl,
                                                    _pd, _pd, _i32]
@@ -227,6 +230,22 @@ def outer_parts(X, y, x, eta: float, lam: float, b: int, s: int, seed: int,
                                         _p(yI, _pd), _p(r, _pd), _p(G, _pd), _p(d, _pd),
                                         _p(c, _pd), _loss_code(loss)))
     return dict(idx=idx, yI=yI, r=r, G=G, delta=d, c=c)
+
+
+def outer_rows(Y, yI, x, eta: float, lam: float, b: int, s: int, loss="logistic") -> dict:
+    """One outer iteration of Algorithm 1 (with decay) on the given sampled rows
+    Y (s*b x n) and labels yI: r, strict block-lower G, delta, c and the new x."""
+    Yr = _f64(Y)
+    sb, n = Yr.shape
+    assert sb == s * b
+    yv, xv = _f64(yI), _f64(x)
+    r, d, c = np.empty(sb), np.empty(sb), np.empty(sb)
+    G = np.empty((sb, sb))
+    xn = np.empty(n)
+    _check(lib().oracle_outer_rows_glm(_p(Yr, _pd), n, _p(yv, _pd), _p(xv, _pd), eta, lam, b, s,
+                                       _p(r, _pd), _p(G, _pd), _p(d, _pd), _p(c, _pd),
+                                       _p(xn, _pd), _loss_code(loss)))
+    return dict(r=r, G=G, delta=d, c=c, x=xn)
 
 
 def inner_corrections(G, r, yI, b: int, s: int, eta: float, lam: float, loss="logistic"):

@@ -12,12 +12,14 @@ import ctypes
 
 from . import _lib
 from ._lib import BF16, CSR, DENSE, F16, F32, FP8E4M3  # noqa: F401
+from ._lib import LOSS_LINEAR, LOSS_LOGISTIC, LOSS_POISSON, LOSSES  # noqa: F401
 
 __all__ = [
     "CasgdError", "dense_matrix", "csr_matrix", "opts", "workspace",
     "casgd_workspace_size", "casgd_reset", "casgd_step", "casgd_fit", "casgd_check",
     "casgd_sample_indices", "casgd_gram_margin", "casgd_recurrence", "casgd_update",
-    "casgd_quantize", "casgd_logloss", "casgd_colstats", "casgd_version",
+    "casgd_quantize", "casgd_logloss", "casgd_loss", "casgd_colstats", "casgd_version",
+    "casgd_recurrence_workspace_size",
     "casgd_path_workspace_size", "casgd_sparse_prepare", "casgd_fit_path",
     "casgd_fit_batch", "casgd_quantize_scaled", "casgd_mlp_features", "casgd_mlp_forward",
     "casgd_mlp_loss_grad", "casgd_mlp_backward", "casgd_adam_step", "casgd_hess_diag",
@@ -114,16 +116,21 @@ def csr_matrix(row_ptr, col_idx, values, n: int) -> MatrixRef:
     return MatrixRef(s, (row_ptr, col_idx, values))
 
 
+def _loss_code(loss) -> int:
+    return LOSSES[loss] if isinstance(loss, str) else int(loss)
+
+
 def opts(recur_prec: int = 0, exec_mode: int = 0, snapshot_every: int = 0, x_history=None,
          t_history=None, spin_limit: int = 0, fused_variant: int = 0, grid_blocks: int = 0,
-         phase_trace=None, rec_split: int = 0):
-    """casgd_opts; phase_trace: device int64 tensor of 8 words per traced outer iteration."""
+         phase_trace=None, rec_split: int = 0, loss=0):
+    """casgd_opts; phase_trace: device int64 tensor of 8 words per traced outer iteration;
+    loss: "logistic", "linear", "poisson" or its code."""
     o = _lib.Opts(recur_prec=recur_prec, exec_mode=exec_mode, snapshot_every=snapshot_every,
                   x_history=_ptr(x_history), t_history=_ptr(t_history), spin_limit=spin_limit,
                   fused_variant=fused_variant, grid_blocks=grid_blocks,
                   phase_trace=_ptr(phase_trace),
                   phase_trace_outer=0 if phase_trace is None else phase_trace.numel() // 8,
-                  rec_split=rec_split)
+                  rec_split=rec_split, loss=_loss_code(loss))
     o._keep = (x_history, t_history, phase_trace)
     return o
 
@@ -209,7 +216,7 @@ def casgd_fit_path(X: MatrixRef, y, x_lanes, lambdas, eta: float, b: int, s: int
 def casgd_fit_batch(problems, spin_limit: int = 0, stream=None):
     """Fit many dense problems in one launch. `problems`: list of dicts with keys
     X (MatrixRef), y, x, eta, lam, b, s, seed and optionally outer_begin,
-    n_outer, ws, groups, variant, recur_prec. Returns the list of workspaces."""
+    n_outer, ws, groups, variant, recur_prec, loss. Returns the list of workspaces."""
     n = len(problems)
     arr = (_lib.Problem * n)()
     keep = []
@@ -224,7 +231,7 @@ def casgd_fit_batch(problems, spin_limit: int = 0, stream=None):
                               outer_begin=q.get("outer_begin", 0), n_outer=q.get("n_outer", 1),
                               ws=_ptr(ws), ws_bytes=ws.numel(), groups=q.get("groups", 0),
                               variant=q.get("variant", 0), recur_prec=q.get("recur_prec", 0),
-                              reserved=0)
+                              loss=_loss_code(q.get("loss", 0)))
     tb = workspace(int(_L().casgd_batch_table_size(n)))
     _check(_L().casgd_fit_batch(arr, n, spin_limit, _ptr(tb), tb.numel(), _stream(stream)))
     return [w for _, w in keep]
@@ -250,12 +257,23 @@ def casgd_gram_margin(X: MatrixRef, x, b: int, s: int, seed: int, outer_iter: in
     return G, r
 
 
+def casgd_recurrence_workspace_size(b: int, s: int) -> int:
+    return int(_L().casgd_recurrence_workspace_size(b, s))
+
+
 def casgd_recurrence(G, r, yI, b: int, s: int, eta: float, lam: float, prec: int = 0,
-                     c=None, delta=None, stream=None):
+                     c=None, delta=None, loss=0, form: int = 0, ws=None, stream=None):
+    """The s residual corrections from device G, r, yI; returns c. form 1: one
+    workgroup; form 2: chain + helper workgroups (b in 16, 32, 64, 128); 0: auto.
+    ws: the flag/exchange workspace (allocated when None); read its flags with
+    casgd_check(ws)."""
     torch = _torch()
     c = c if c is not None else torch.empty(s * b, dtype=torch.float32, device="cuda")
-    _check(_L().casgd_recurrence(_ptr(G), _ptr(r), _ptr(yI), b, s, eta, lam, prec, _ptr(c),
-                                 _ptr(delta), _stream(stream)))
+    if ws is None:
+        ws = workspace(casgd_recurrence_workspace_size(b, s))
+    _check(_L().casgd_recurrence(_ptr(G), _ptr(r), _ptr(yI), b, s, eta, lam, prec,
+                                 _loss_code(loss), form, _ptr(c), _ptr(delta), _ptr(ws),
+                                 ws.numel(), _stream(stream)))
     return c
 
 
@@ -396,6 +414,19 @@ def casgd_logloss(X: MatrixRef, y, xs, stream=None):
     ws = workspace(need)
     _check(_L().casgd_logloss(X.ref(), _ptr(y), _ptr(xs2), count, xs2.stride(0), _ptr(out),
                               _ptr(ws), ws.numel(), _stream(stream)))
+    return out if xs.dim() == 2 else out[0]
+
+
+def casgd_loss(X: MatrixRef, y, xs, loss="logistic", stream=None):
+    """Mean loss (logistic, linear or Poisson, Sec. 2.1) for each row of xs
+    (k x n) or for a single x (n); FP64 results on the device."""
+    torch = _torch()
+    xs2 = xs if xs.dim() == 2 else xs.view(1, -1)
+    count = xs2.shape[0]
+    out = torch.empty(count, dtype=torch.float64, device="cuda")
+    ws = workspace(int(_L().casgd_logloss_workspace_size(count)))
+    _check(_L().casgd_loss(X.ref(), _ptr(y), _ptr(xs2), count, xs2.stride(0), _loss_code(loss),
+                           _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
     return out if xs.dim() == 2 else out[0]
 
 

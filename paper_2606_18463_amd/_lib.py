@@ -20,6 +20,8 @@ STATUS_NAMES = {0: "CASGD_OK", -1: "CASGD_EINVAL", -2: "CASGD_EUNSUPPORTED", -3:
 
 F32, BF16, F16, FP8E4M3 = 0, 1, 2, 3
 DENSE, CSR = 0, 1
+LOSS_LOGISTIC, LOSS_LINEAR, LOSS_POISSON = 0, 1, 2
+LOSSES = {"logistic": LOSS_LOGISTIC, "linear": LOSS_LINEAR, "poisson": LOSS_POISSON}
 
 
 class Matrix(ctypes.Structure):
@@ -32,14 +34,14 @@ class Opts(ctypes.Structure):
     _fields_ = [("recur_prec", c_i32), ("exec_mode", c_i32), ("snapshot_every", c_i64),
                 ("x_history", c_vp), ("t_history", c_vp), ("spin_limit", c_i64),
                 ("fused_variant", c_i32), ("grid_blocks", c_i32), ("phase_trace", c_vp),
-                ("phase_trace_outer", c_i64), ("rec_split", c_i32)]
+                ("phase_trace_outer", c_i64), ("rec_split", c_i32), ("loss", c_i32)]
 
 
 class Problem(ctypes.Structure):
     _fields_ = [("X", Matrix), ("y", c_vp), ("x", c_vp), ("eta", c_dbl), ("lam", c_dbl),
                 ("b", c_i32), ("s", c_i32), ("seed", c_u64), ("outer_begin", c_u64),
                 ("n_outer", c_i64), ("ws", c_vp), ("ws_bytes", c_sz), ("groups", c_i32),
-                ("variant", c_i32), ("recur_prec", c_i32), ("reserved", c_i32)]
+                ("variant", c_i32), ("recur_prec", c_i32), ("loss", c_i32)]
 
 
 PM = ctypes.POINTER(Matrix)
@@ -66,8 +68,9 @@ SIGNATURES = {
     "casgd_sample_indices": (c_i32, [c_u64, c_u64, c_i64, c_i64, c_vp, c_vp]),
     "casgd_gram_margin": (c_i32, [PM, c_vp, c_i32, c_i32, c_u64, c_u64, c_vp, c_vp, c_vp, c_sz,
                                   c_vp]),
-    "casgd_recurrence": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_dbl, c_dbl, c_i32, c_vp, c_vp,
-                                 c_vp]),
+    "casgd_recurrence_workspace_size": (c_sz, [c_i32, c_i32]),
+    "casgd_recurrence": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_dbl, c_dbl, c_i32, c_i32, c_i32,
+                                 c_vp, c_vp, c_vp, c_sz, c_vp]),
     "casgd_update": (c_i32, [PM, c_vp, c_vp, c_i32, c_i32, c_u64, c_u64, c_dbl, c_dbl, c_vp,
                              c_sz, c_vp]),
     "casgd_quantize": (c_i32, [c_vp, c_i64, c_i64, c_i64, c_i32, c_vp, c_i64, c_vp, c_vp]),
@@ -88,6 +91,7 @@ SIGNATURES = {
     "casgd_hess_diag": (c_i32, [PM, c_vp, c_dbl, c_vp, c_vp, c_sz, c_vp]),
     "casgd_logloss_workspace_size": (c_sz, [c_i64]),
     "casgd_logloss": (c_i32, [PM, c_vp, c_vp, c_i64, c_i64, c_vp, c_vp, c_sz, c_vp]),
+    "casgd_loss": (c_i32, [PM, c_vp, c_vp, c_i64, c_i64, c_i32, c_vp, c_vp, c_sz, c_vp]),
     "casgd_colstats_workspace_size": (c_sz, [PM]),
     "casgd_colstats": (c_i32, [PM, c_vp, c_vp, c_sz, c_vp]),
 }

@@ -238,6 +238,14 @@ static casgd_status check_csr(const casgd_matrix* X) {
     return CASGD_OK;
 }
 
+casgd_status check_loss(int loss) {
+    if (loss != CASGD_LOSS_LOGISTIC && loss != CASGD_LOSS_LINEAR && loss != CASGD_LOSS_POISSON) {
+        set_error("loss must be 0 (logistic), 1 (linear) or 2 (Poisson), got %d", loss);
+        return CASGD_EINVAL;
+    }
+    return CASGD_OK;
+}
+
 static casgd_status check_scalars(double eta, double lambda) {
     if (!(eta > 0) || !std::isfinite(eta) || !(lambda >= 0) || !std::isfinite(lambda)) {
         set_error("need eta > 0 and lambda >= 0, both finite (eta=%g, lambda=%g)", eta, lambda);
@@ -299,6 +307,8 @@ static casgd_status make_dense(const casgd_matrix* X, const float* y, float* x, 
         P->kchunk = L->kchunk;
         P->nslices = L->nslices;
     }
+    P->loss = o ? o->loss : CASGD_LOSS_LOGISTIC;
+    if ((rc = check_loss(P->loss)) != CASGD_OK) return rc;
     if (o && o->snapshot_every > 0) {
         if (!o->x_history) {
             set_error("snapshot_every > 0 needs x_history");
@@ -490,6 +500,7 @@ casgd_status casgd_fit_batch(const casgd_problem* probs, int32_t count, int64_t 
         std::memset(&o, 0, sizeof o);
         o.recur_prec = q.recur_prec;
         o.fused_variant = q.variant;
+        o.loss = q.loss;
         rc = make_dense(&q.X, q.y, q.x, q.eta, q.lambda, q.b, q.s, q.seed, &o, q.ws, q.ws_bytes,
                         &D[i], &L, true);
         if (rc != CASGD_OK) {
@@ -607,9 +618,19 @@ casgd_status casgd_gram_margin(const casgd_matrix* X, const float* x, int32_t b,
     return run_margin_reduce(P, P.rp[0], outer_iter, r, st);
 }
 
+// Workspace of casgd_recurrence: the flag words, then the exchange words of
+// the multi-workgroup form (2 * sb values of up to two 64-bit words).
+static size_t rec_ws_pub_offset() { return align256((size_t)FLAG_WORDS * 4); }
+
+size_t casgd_recurrence_workspace_size(int32_t b, int32_t s) {
+    if (b < 1 || s < 1 || (int64_t)b * s > 4096) return 0;
+    return rec_ws_pub_offset() + align256((size_t)b * s * 4 * sizeof(unsigned long long));
+}
+
 casgd_status casgd_recurrence(const float* G, const float* r, const float* yI, int32_t b,
-                              int32_t s, double eta, double lambda, int32_t prec, float* c,
-                              float* delta, void* stream) {
+                              int32_t s, double eta, double lambda, int32_t prec, int32_t loss,
+                              int32_t form, float* c, float* delta, void* ws, size_t ws_bytes,
+                              void* stream) {
     casgd_status rc;
     if ((s > 1 && !G) || !r || !yI || !c) {
         set_error("G, r, yI and c must not be NULL");
@@ -617,10 +638,24 @@ casgd_status casgd_recurrence(const float* G, const float* r, const float* yI, i
     }
     if ((rc = check_bs(b, s)) != CASGD_OK) return rc;
     if ((rc = check_scalars(eta, lambda)) != CASGD_OK) return rc;
+    if ((rc = check_loss(loss)) != CASGD_OK) return rc;
     if (prec != 0 && prec != 32 && prec != 64) {
         set_error("prec must be 0, 32 or 64");
         return CASGD_EINVAL;
     }
+    const bool multi_ok = (b == 16 || b == 32 || b == 64 || b == 128) && s > 1;
+    if (form == 0) form = multi_ok ? 2 : 1;
+    if (form != 1 && form != 2) {
+        set_error("form must be 0, 1 or 2 (got %d)", form);
+        return CASGD_EINVAL;
+    }
+    if (form == 2 && !multi_ok) {
+        set_error("form 2 needs b = 16, 32, 64 or 128 and s > 1");
+        return CASGD_EUNSUPPORTED;
+    }
+    if ((form == 2 || ws) &&
+        (rc = check_ws(ws, ws_bytes, casgd_recurrence_workspace_size(b, s))) != CASGD_OK)
+        return rc;
     Dense P;
     std::memset(&P, 0, sizeof P);
     P.b = b;
@@ -632,8 +667,18 @@ casgd_status casgd_recurrence(const float* G, const float* r, const float* yI, i
     P.alpha = (float)P.alpha_d;
     P.beta = (float)P.beta_d;
     P.m = 1;
+    P.loss = loss;
+    if (ws) {
+        P.flags = static_cast<unsigned*>(ws);
+        P.pub = reinterpret_cast<unsigned long long*>(static_cast<char*>(ws) + rec_ws_pub_offset());
+    }
     const bool fp64 = prec == 64 || (prec == 0 && P.sb >= 512);
-    return run_recurrence(P, G, nullptr, 0, r, yI, c, delta, fp64, (hipStream_t)stream);
+    hipStream_t st = (hipStream_t)stream;
+    if (form == 1) return run_recurrence(P, G, nullptr, 0, r, yI, c, delta, fp64, st);
+    // the exchange words start from zero (the chain workgroup clears them when done)
+    if ((rc = run_zero(reinterpret_cast<unsigned*>(P.pub), (int64_t)P.sb * 8, st)) != CASGD_OK)
+        return rc;
+    return run_recurrence_multi(P, G, r, yI, c, delta, fp64, 1ull << 24, st);
 }
 
 casgd_status casgd_update(const casgd_matrix* X, float* x, const float* c, int32_t b, int32_t s,
@@ -788,19 +833,26 @@ size_t casgd_logloss_workspace_size(int64_t count) {
     return count > 0 ? (size_t)count * kLossBlocks * sizeof(double) : 0;
 }
 
-casgd_status casgd_logloss(const casgd_matrix* X, const float* y, const float* xs, int64_t count,
-                           int64_t x_stride, double* out, void* ws, size_t ws_bytes,
-                           void* stream) {
+casgd_status casgd_loss(const casgd_matrix* X, const float* y, const float* xs, int64_t count,
+                        int64_t x_stride, int32_t loss, double* out, void* ws, size_t ws_bytes,
+                        void* stream) {
     if (!X || !y || !xs || !out || count < 1 || x_stride < X->n) {
-        set_error("bad arguments to casgd_logloss");
+        set_error("bad arguments to casgd_loss");
         return CASGD_EINVAL;
     }
     casgd_status rc;
+    if ((rc = check_loss(loss)) != CASGD_OK) return rc;
     if (X->layout == CASGD_DENSE && (rc = check_dense(X)) != CASGD_OK) return rc;
     if (X->layout == CASGD_CSR && (rc = check_csr(X)) != CASGD_OK) return rc;
     if ((rc = check_ws(ws, ws_bytes, casgd_logloss_workspace_size(count))) != CASGD_OK) return rc;
-    return run_logloss(X, y, xs, count, x_stride, out, static_cast<double*>(ws),
-                       (hipStream_t)stream);
+    return run_loss(X, y, xs, count, x_stride, loss, out, static_cast<double*>(ws),
+                    (hipStream_t)stream);
+}
+
+casgd_status casgd_logloss(const casgd_matrix* X, const float* y, const float* xs, int64_t count,
+                           int64_t x_stride, double* out, void* ws, size_t ws_bytes,
+                           void* stream) {
+    return casgd_loss(X, y, xs, count, x_stride, CASGD_LOSS_LOGISTIC, out, ws, ws_bytes, stream);
 }
 
 size_t casgd_colstats_workspace_size(const casgd_matrix* X) {

@@ -23,6 +23,21 @@ __device__ __forceinline__ int64_t sample_row(uint64_t seed, uint64_t t, uint64_
     return (int64_t)__umul64hi(splitmix64(seed, t), m);
 }
 
+// ------------------------------------------------------------------ losses
+// The three generalized linear models of Sec. 2.1; the residual is
+// delta = -dL/dz at the margin z (Sec. 3.1):
+//   logistic  L = log(1 + exp(-y z))      delta = y / (1 + exp(y z)) = y (1 - sigma(y z))
+//   linear    L = (z - y)^2 / 2           delta = y - z
+//   Poisson   L = exp(z) - y z            delta = y - exp(z)
+enum : int { LOSS_LOGISTIC = 0, LOSS_LINEAR = 1, LOSS_POISSON = 2 };
+
+template <typename ACC>
+__device__ __forceinline__ ACC glm_delta(ACC z, ACC y, int loss) {
+    if (loss == LOSS_LINEAR) return y - z;
+    if (loss == LOSS_POISSON) return y - exp(z);
+    return y / ((ACC)1 + exp(y * z));
+}
+
 // ----------------------------------------------------------- storage types
 enum : int { DT_F32 = 0, DT_BF16 = 1, DT_F16 = 2, DT_FP8 = 3 };
 

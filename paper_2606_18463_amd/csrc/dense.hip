@@ -232,7 +232,7 @@ static casgd_status launch_rec_multi_acc(const Dense& P, const float* G, const f
     }
 }
 
-static casgd_status run_rec_multi(const Dense& P, const float* G, const float* r, const float* y,
+casgd_status run_recurrence_multi(const Dense& P, const float* G, const float* r, const float* y,
                                   float* c, float* delta_out, bool fp64, unsigned long long spin,
                                   hipStream_t st) {
     return fp64 ? launch_rec_multi_acc<double>(P, G, r, y, c, delta_out, spin, st)
@@ -415,7 +415,7 @@ casgd_status run_fit(const Dense& P, int dtype, uint64_t h0, int64_t H, const Fi
             if ((rc = run_gather_reduce(P, dtype, h + 1, more ? 1 : 0, P.rp[0], h, P.r, st)) !=
                 CASGD_OK)
                 return rc;
-            if ((rc = run_rec_multi(P, P.G[0], P.r, P.yI[slot_of_host(h)], P.c, nullptr,
+            if ((rc = run_recurrence_multi(P, P.G[0], P.r, P.yI[slot_of_host(h)], P.c, nullptr,
                                     plan.recur64 != 0, plan.spin, st)) != CASGD_OK)
                 return rc;
         } else {

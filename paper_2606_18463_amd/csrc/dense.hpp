@@ -61,6 +61,7 @@ struct Dense {
     int gsize;              // workgroups running this problem
     int recur64;            // FP64 recurrence
     int tpr;                // threads per row of the recurrence
+    int loss;               // LOSS_* (residual formula of the recurrence)
 };
 
 __device__ __forceinline__ int slot_of(uint64_t h) { return (int)(h % 3ull); }
@@ -558,7 +559,8 @@ __device__ __forceinline__ void update_margin_slice(const Dense& P, int slice, c
 // loop) with L2 decay, in precision ACC (the u_c slot), by one workgroup of
 // NT threads. TPR threads (a power of two) cooperate on one row of a block.
 //   z_t = beta^j r_t + alpha * sum_{i<j} beta^(j-1-i) (G_{t, block i} . delta_i)
-//   delta_t = y_t / (1 + exp(y_t z_t));  c_t = beta^(s-1-j) delta_t
+//   delta_t = glm_delta(z_t, y_t) (logistic: y_t / (1 + exp(y_t z_t)));
+//   c_t = beta^(s-1-j) delta_t
 // r_t and y_t come either from the partial margins rp (summed over slices,
 // times the row scale) and the gathered labels, or directly from r_in / y_in.
 // Writes c (global or LDS) and optionally delta_out. Uses LDS `dl` (sb ACC)
@@ -650,8 +652,8 @@ __device__ __forceinline__ void recurrence(const Dense& P, const float* G, const
                     yv = (ACC)pick3(P.yI, slot)[t];
                 }
                 const ACC z = pw[j] * r + alpha * acc;
-                const ACC d = yv / ((ACC)1 + exp(yv * z));
-                if (!isfinite(z)) raise_flag(P.flags, FLAG_NONFINITE);
+                const ACC d = glm_delta<ACC>(z, yv, P.loss);
+                if (!isfinite(z) || !isfinite(d)) raise_flag(P.flags, FLAG_NONFINITE);
                 dl[t] = d;
                 c[t] = (float)(pw[s - 1 - j] * d);
                 if (delta_out) delta_out[t] = (float)d;

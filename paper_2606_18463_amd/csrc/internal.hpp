@@ -55,7 +55,11 @@ casgd_status run_margin_reduce(const Dense& P, const float* rp, uint64_t h, floa
 casgd_status run_recurrence(const Dense& P, const float* G, const float* rp, uint64_t h,
                             const float* r_in, const float* y_in, float* c, float* delta_out,
                             bool fp64, hipStream_t st);
+casgd_status run_recurrence_multi(const Dense& P, const float* G, const float* r, const float* y,
+                                  float* c, float* delta_out, bool fp64, unsigned long long spin,
+                                  hipStream_t st);
 casgd_status run_update(const Dense& P, int dtype, const float* c, uint64_t h, hipStream_t st);
+casgd_status check_loss(int loss);
 casgd_status run_zero(unsigned* p, int64_t words, hipStream_t st);
 casgd_status run_fit_batch(const Dense* table_dev, const int2* wgmap_dev, int grid, int dtype,
                            size_t lds, unsigned long long spin, hipStream_t st);

@@ -78,11 +78,19 @@ __device__ __forceinline__ double softplus(double v) {
     return (v > 0 ? v : 0.0) + log1p(exp(-fabs(v)));
 }
 
+// L(z, y) of Sec. 2.1 in FP64: logistic through the stable softplus, linear
+// (z - y)^2 / 2, Poisson exp(z) - y z.
+__device__ __forceinline__ double glm_loss(double z, double y, int loss) {
+    if (loss == LOSS_LINEAR) return 0.5 * (z - y) * (z - y);
+    if (loss == LOSS_POISSON) return exp(z) - y * z;
+    return softplus(-y * z);
+}
+
 template <int DT>
 __global__ __launch_bounds__(256) void k_loss_dense(const void* Xv, const float* scale,
                                                     int64_t m, int64_t n, int64_t ld,
                                                     const float* y, const float* xs,
-                                                    int64_t x_stride, double* partial) {
+                                                    int64_t x_stride, int loss, double* partial) {
     using T = typename Store<DT>::T;
     constexpr int VEC = Store<DT>::kVec;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -101,7 +109,7 @@ __global__ __launch_bounds__(256) void k_loss_dense(const void* Xv, const float*
         }
         z = group_sum<64>(z);
         if (scale) z *= scale[i];
-        acc += softplus(-(double)y[i] * (double)z);
+        acc += glm_loss((double)z, (double)y[i], loss);
     }
     __shared__ double s[4];
     if (lane == 0) s[w] = acc;
@@ -111,7 +119,7 @@ __global__ __launch_bounds__(256) void k_loss_dense(const void* Xv, const float*
 
 __global__ __launch_bounds__(256) void k_loss_csr(const int64_t* rp, const int32_t* ci,
                                                   const float* va, int64_t m, const float* y,
-                                                  const float* xs, int64_t x_stride,
+                                                  const float* xs, int64_t x_stride, int loss,
                                                   double* partial) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t k = blockIdx.y;
@@ -121,7 +129,7 @@ __global__ __launch_bounds__(256) void k_loss_csr(const int64_t* rp, const int32
         float z = 0.f;
         for (int64_t p = rp[i] + lane; p < rp[i + 1]; p += 64) z = fmaf(va[p], x[ci[p]], z);
         z = group_sum<64>(z);
-        acc += softplus(-(double)y[i] * (double)z);
+        acc += glm_loss((double)z, (double)y[i], loss);
     }
     __shared__ double s[4];
     if (lane == 0) s[w] = acc;
@@ -138,29 +146,29 @@ __global__ void k_loss_final(const double* partial, int64_t count, int nblk, int
     out[k] = t / (double)m;
 }
 
-casgd_status run_logloss(const casgd_matrix* X, const float* y, const float* xs, int64_t count,
-                         int64_t x_stride, double* out, double* partial, hipStream_t st) {
+casgd_status run_loss(const casgd_matrix* X, const float* y, const float* xs, int64_t count,
+                      int64_t x_stride, int loss, double* out, double* partial, hipStream_t st) {
     const dim3 grid(kLossBlocks, (unsigned)count);
     if (X->layout == CASGD_CSR) {
         hipLaunchKernelGGL(k_loss_csr, grid, dim3(256), 0, st, X->row_ptr, X->col_idx,
-                           static_cast<const float*>(X->values), X->m, y, xs, x_stride, partial);
+                           static_cast<const float*>(X->values), X->m, y, xs, x_stride, loss, partial);
     } else {
         switch (X->dtype) {
             case DT_F32:
                 hipLaunchKernelGGL(k_loss_dense<DT_F32>, grid, dim3(256), 0, st, X->values,
-                                   X->row_scale, X->m, X->n, X->ld, y, xs, x_stride, partial);
+                                   X->row_scale, X->m, X->n, X->ld, y, xs, x_stride, loss, partial);
                 break;
             case DT_BF16:
                 hipLaunchKernelGGL(k_loss_dense<DT_BF16>, grid, dim3(256), 0, st, X->values,
-                                   X->row_scale, X->m, X->n, X->ld, y, xs, x_stride, partial);
+                                   X->row_scale, X->m, X->n, X->ld, y, xs, x_stride, loss, partial);
                 break;
             case DT_F16:
                 hipLaunchKernelGGL(k_loss_dense<DT_F16>, grid, dim3(256), 0, st, X->values,
-                                   X->row_scale, X->m, X->n, X->ld, y, xs, x_stride, partial);
+                                   X->row_scale, X->m, X->n, X->ld, y, xs, x_stride, loss, partial);
                 break;
             default:
                 hipLaunchKernelGGL(k_loss_dense<DT_FP8>, grid, dim3(256), 0, st, X->values,
-                                   X->row_scale, X->m, X->n, X->ld, y, xs, x_stride, partial);
+                                   X->row_scale, X->m, X->n, X->ld, y, xs, x_stride, loss, partial);
                 break;
         }
     }

@@ -15,8 +15,8 @@ casgd_status run_quantize(const float* src, int64_t m, int64_t n, int64_t ld_src
                           hipStream_t st);
 constexpr int kLossBlocks = 256;     // partial sums per weight vector
 constexpr int kStatRowBlocks = 64;   // row blocks of the column statistics
-casgd_status run_logloss(const casgd_matrix* X, const float* y, const float* xs, int64_t count,
-                         int64_t x_stride, double* out, double* partial, hipStream_t st);
+casgd_status run_loss(const casgd_matrix* X, const float* y, const float* xs, int64_t count,
+                      int64_t x_stride, int loss, double* out, double* partial, hipStream_t st);
 casgd_status run_colstats(const casgd_matrix* X, float* stats, double* partial, hipStream_t st);
 
 casgd_status run_mlp_features(const float* stats, int64_t N, const float* norm, float* feats,

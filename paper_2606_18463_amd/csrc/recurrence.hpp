@@ -2,7 +2,8 @@
 // the L2 decay) spread over several workgroups of one launch.
 //
 //   z_j = beta^j r_j + alpha sum_{i<j} beta^(j-1-i) G_{j,i} delta_i,
-//   delta_j = y_j / (1 + exp(y_j z_j)),   c_j = beta^(s-1-j) delta_j.
+//   delta_j = glm_delta(z_j, y_j) (logistic: y_j / (1 + exp(y_j z_j))),
+//   c_j = beta^(s-1-j) delta_j.
 //
 // The chain over j is sequential, but G is known before it starts. The main
 // workgroup (blockIdx 0) runs the chain and adds only the last W column
@@ -193,8 +194,8 @@ __device__ void recurrence_multi(const Dense& P, const float* G, const float* r,
                     const int t = j * b + q;
                     const ACC rv = (ACC)ry[p].x, yv = (ACC)ry[p].y;
                     const ACC z = pw[j] * rv + alpha * (far + nsum);
-                    const ACC d = yv / ((ACC)1 + exp(yv * z));
-                    if (!isfinite(z)) raise_flag(P.flags, FLAG_NONFINITE);
+                    const ACC d = glm_delta<ACC>(z, yv, P.loss);
+                    if (!isfinite(z) || !isfinite(d)) raise_flag(P.flags, FLAG_NONFINITE);
                     dl[t] = d;
                     c[t] = (float)(pw[s - 1 - j] * d);
                     if (delta_out) delta_out[t] = (float)d;

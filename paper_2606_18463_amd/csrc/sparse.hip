@@ -382,6 +382,8 @@ casgd_status sparse_fit(const casgd_matrix* X, const float* y, float* x_lanes,
     S.Hp = P.Hp;
     S.maxlen = SL.maxlen;
     S.flags = at<unsigned>(ws, SL.off_flags);
+    S.loss = opts ? opts->loss : 0;
+    if ((rc = check_loss(S.loss)) != CASGD_OK) return rc;
     for (int k = 0; k < 3; ++k) {
         S.Yh[k] = at<float>(ws, SL.off_Yh[k]);
         S.tcol[k] = at<int32_t>(ws, SL.off_tcol[k]);

@@ -64,6 +64,7 @@ struct Sparse {
     int64_t* ptrace;        // phase clock (8 words per outer iteration) or nullptr
     int64_t ptrace_outer;
     Dense gram;             // view for the head-panel Gram (MFMA tiles)
+    int loss;               // LOSS_* (residual formula of the recurrence)
 };
 
 template <typename T>
@@ -663,8 +664,8 @@ __device__ __forceinline__ void sparse_recurrence(const Sparse& S, const float* 
                 ACC d = 0;
                 if (l < nl) {
                     const ACC z = pw[l * (s + 1) + j] * (ACC)rv + alpha * tot;
-                    d = (ACC)yv / ((ACC)1 + exp((ACC)yv * z));
-                    if (!isfinite(z)) raise_flag(S.flags, FLAG_NONFINITE);
+                    d = glm_delta<ACC>(z, (ACC)yv, S.loss);
+                    if (!isfinite(z) || !isfinite(d)) raise_flag(S.flags, FLAG_NONFINITE);
                     S.c[(int64_t)t * L + l0 + l] = (float)(pw[l * (s + 1) + (s - 1 - j)] * d);
                     if (K > 1 && j + 1 < s) pub_put(S.pub + 2 * ((int64_t)t * L + l0 + l), d);
                 }

@@ -82,18 +82,39 @@ def test_fit_argument_errors_before_device_work():
     o = _lib.Opts(snapshot_every=5)
     assert lib.casgd_fit(ctypes.byref(X), 0x2000, 0x3000, 0.5, 0.0, 16, 4, 1, 0, 1,
                          ctypes.byref(o), ws, need.value, None) == -1
+    o = _lib.Opts(loss=3)
+    assert lib.casgd_fit(ctypes.byref(X), 0x2000, 0x3000, 0.5, 0.0, 16, 4, 1, 0, 1,
+                         ctypes.byref(o), ws, need.value, None) == -1
+    assert b"loss" in lib.casgd_last_error()
 
 
 def test_other_entry_points_validate():
     lib = _lib.load()
     assert lib.casgd_sample_indices(1, 0, 10, 0, 0x1000, None) == -1
-    assert lib.casgd_recurrence(None, 0x1000, 0x1000, 16, 4, 0.5, 0.0, 0, 0x1000, None,
-                                None) == -1
-    assert lib.casgd_recurrence(0x1000, 0x1000, 0x1000, 16, 4, 0.5, 0.0, 16, 0x1000, None,
-                                None) == -1
+    assert lib.casgd_recurrence(None, 0x1000, 0x1000, 16, 4, 0.5, 0.0, 0, 0, 1, 0x1000, None,
+                                None, 0, None) == -1
+    assert lib.casgd_recurrence(0x1000, 0x1000, 0x1000, 16, 4, 0.5, 0.0, 16, 0, 1, 0x1000, None,
+                                None, 0, None) == -1
+    # unknown loss, unknown form, form 2 for an unsupported b, form 2 without workspace
+    assert lib.casgd_recurrence(0x1000, 0x1000, 0x1000, 16, 4, 0.5, 0.0, 0, 3, 1, 0x1000, None,
+                                None, 0, None) == -1
+    assert lib.casgd_recurrence(0x1000, 0x1000, 0x1000, 16, 4, 0.5, 0.0, 0, 0, 3, 0x1000, None,
+                                None, 0, None) == -1
+    assert lib.casgd_recurrence(0x1000, 0x1000, 0x1000, 24, 4, 0.5, 0.0, 0, 0, 2, 0x1000, None,
+                                None, 0, None) == -2
+    assert lib.casgd_recurrence(0x1000, 0x1000, 0x1000, 16, 4, 0.5, 0.0, 0, 0, 2, 0x1000, None,
+                                None, 0, None) == -1
+    need = lib.casgd_recurrence_workspace_size(64, 16)
+    assert need >= 736 * 4 + 64 * 16 * 32
+    assert lib.casgd_recurrence(0x1000, 0x1000, 0x1000, 64, 16, 0.5, 0.0, 0, 0, 2, 0x1000, None,
+                                0x100000, need - 256, None) == -3
+    assert lib.casgd_recurrence_workspace_size(64, 65) == 0
     assert lib.casgd_quantize(None, 4, 4, 4, _lib.BF16, 0x1000, 8, None, None) == -1
     assert lib.casgd_quantize(0x1000, 4, 4, 4, _lib.FP8E4M3, 0x1000, 16, None, None) == -1
     X = _dense()
     assert lib.casgd_logloss(ctypes.byref(X), 0x1000, 0x1000, 2, 64, 0x1000, None, 0,
                              None) == -1
     assert lib.casgd_logloss_workspace_size(3) == 3 * 256 * 8
+    # the loss selector is validated
+    assert lib.casgd_loss(ctypes.byref(X), 0x1000, 0x1000, 2, 64, 5, 0x1000, 0x1000, 4096,
+                          None) == -1

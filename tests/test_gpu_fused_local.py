@@ -1,0 +1,216 @@
+"""Element-by-element parity of every execution form with the FP64 oracle, one
+outer iteration at a time (on an MI355X).
+
+Each fit runs with a snapshot of x after every outer iteration. For every
+outer iteration h the oracle takes the GPU's own x_{h-1} and the exact stored
+values of the rows that h samples, and computes x_h (Algorithm 1 with the L2
+decay); every entry of the GPU's x_h must lie within the first-order bound
+of tests/_bounds.py (FP32 margins, Gram and update; corrections in the
+kernel's precision). This checks the pieces of the fused kernels that only
+run inside a fit -- the chain + helper recurrence with its exchange words, the
+claimed Gram units, the margin hand-off between phases -- entry by entry, and
+not only through the trajectory norm.
+
+The recurrence entry point is checked the same way for both of its forms
+(one workgroup; chain + helpers) against the oracle's corrections.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import reference as R  # noqa: E402
+from workloads import dense_glm  # noqa: E402
+from _bounds import U32, U64, assert_within, outer_bound, rec_prec_u, recurrence_bound  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def cg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_18463_amd as cg
+    cg._lib.load()
+    return cg
+
+
+def _dev(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+ETA = {"logistic": 0.5, "linear": 0.1, "poisson": 0.05}
+
+
+@pytest.fixture(scope="module")
+def data():
+    """20000 x 520 dense problems (520 = 8 Gram K steps of 64 plus a ragged
+    tail for every storage width), one per loss."""
+    return {loss: dense_glm(20000, 520, 17, loss, var=1 / 520, dtype=np.float32)
+            for loss in ("logistic", "linear", "poisson")}
+
+
+# ---------------------------------------------------------------- recurrence
+
+REC_SHAPES = [(16, 4), (16, 32), (32, 8), (32, 32), (64, 4), (64, 16), (64, 32), (128, 3),
+              (128, 8), (128, 32), (24, 5), (3, 11)]
+
+
+@pytest.mark.parametrize("b,s", REC_SHAPES)
+@pytest.mark.parametrize("form", [1, 2])
+@pytest.mark.parametrize("prec", [32, 64])
+@pytest.mark.parametrize("loss", ["logistic", "linear", "poisson"])
+def test_recurrence_forms_vs_oracle(cg, data, b, s, form, prec, loss):
+    if form == 2 and b not in (16, 32, 64, 128):
+        pytest.skip("the chain + helper form needs b in {16, 32, 64, 128}")
+    p = data[loss]
+    x = np.random.default_rng(b * s).standard_normal(520) * 0.1
+    eta, lam = ETA[loss], 1e-3
+    parts = R.outer_parts(p.X, p.y, x, eta, lam, b, s, 42, 1, loss=loss)
+    G32 = parts["G"].astype(np.float32)
+    r32 = parts["r"].astype(np.float32)
+    y32 = parts["yI"].astype(np.float32)
+    d = torch.empty(s * b, dtype=torch.float32, device="cuda")
+    ws = cg.workspace(cg.casgd_recurrence_workspace_size(b, s))
+    c = cg.casgd_recurrence(_dev(G32), _dev(r32), _dev(y32), b, s, eta, lam, prec, delta=d,
+                            loss=loss, form=form, ws=ws)
+    cg.casgd_check(ws)
+    # the exact corrections of the FP32 inputs, and the bound for computing
+    # them in the kernel's precision
+    dex, cex = R.inner_corrections(G32.astype(np.float64), r32.astype(np.float64),
+                                   y32.astype(np.float64), b, s, eta, lam, loss=loss)
+    zero = np.zeros((s * b, s * b))
+    ed, ec = recurrence_bound(G32.astype(np.float64), r32.astype(np.float64),
+                              y32.astype(np.float64), dex, b, s, eta, lam, loss,
+                              np.zeros(s * b), zero, U64 if prec == 64 else U32)
+    assert_within(d.cpu().numpy(), dex, 1.5 * ed + 1e-30, "delta")
+    assert_within(c.cpu().numpy(), cex, 1.5 * ec + 1e-30, "c")
+    # and the oracle's corrections of the unrounded inputs, with their rounding
+    ed2, ec2 = recurrence_bound(parts["G"], parts["r"], parts["yI"], parts["delta"], b, s, eta,
+                                lam, loss, U32 * np.abs(parts["r"]), U32 * np.abs(parts["G"]),
+                                U64 if prec == 64 else U32)
+    assert_within(c.cpu().numpy(), parts["c"], 1.5 * ec2 + 1e-30, "c vs unrounded inputs")
+
+
+def test_recurrence_forms_bitwise_reproducible(cg, data):
+    p = data["logistic"]
+    b, s = 64, 16
+    parts = R.outer_parts(p.X, p.y, np.zeros(520), 0.5, 1e-3, b, s, 42, 3)
+    G, r, y = _dev(parts["G"]), _dev(parts["r"]), _dev(parts["yI"])
+    ws = cg.workspace(cg.casgd_recurrence_workspace_size(b, s))
+    outs = [cg.casgd_recurrence(G, r, y, b, s, 0.5, 1e-3, 64, form=2, ws=ws) for _ in range(3)]
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+
+
+# ------------------------------------------------- whole fits, per outer step
+
+def _stored(cg, X32, fmt):
+    code = {"f32": cg.F32, "bf16": cg.BF16, "f16": cg.F16, "fp8": cg.FP8E4M3}[fmt]
+    dst, sc = cg.casgd_quantize(_dev(X32), code)
+    torch.cuda.synchronize()
+    return cg.dense_matrix(dst, sc, n=X32.shape[1]), (dst, sc)
+
+
+def local_check(cg, X, exact_rows, y, n, b, s, eta, lam, seed, H, loss="logistic",
+                scaled=False, what="", **opts_kw):
+    """Fit H outer iterations with a snapshot after each; check each one
+    against the oracle's outer iteration from the GPU's previous iterate.
+    exact_rows(idx) -> exact FP64 values of the stored rows idx."""
+    hist = torch.zeros(H, n, device="cuda")
+    x = torch.zeros(n, device="cuda")
+    o = cg.opts(snapshot_every=1, x_history=hist, loss=loss, **opts_kw)
+    ws = cg.casgd_fit(X, _dev(y), x, eta, lam, b, s, seed, 0, H, opts=o)
+    cg.casgd_check(ws)
+    xs = hist.cpu().numpy().astype(np.float64)
+    assert np.array_equal(xs[-1], x.cpu().numpy().astype(np.float64))
+    prev = np.zeros(n)
+    u = rec_prec_u(opts_kw.get("recur_prec", 0), s * b)
+    worst = 0.0
+    m = X.m
+    for h in range(H):
+        idx = R.sample_indices(seed, h * s * b, s * b, m)
+        bound, ex = outer_bound(exact_rows(idx), prev, y[idx].astype(np.float64), b, s, eta, lam,
+                                loss, u_acc=u, scaled=scaled)
+        worst = max(worst, assert_within(xs[h], ex["x"], bound, f"{what} outer {h}"))
+        prev = xs[h]
+    return worst
+
+
+FORMS = [dict(exec_mode=1, fused_variant=3), dict(exec_mode=1, fused_variant=2),
+         dict(exec_mode=1, fused_variant=1), dict(exec_mode=2)]
+
+
+@pytest.mark.parametrize("b,s", [(16, 8), (32, 16), (64, 4), (64, 16), (64, 32), (128, 8)])
+@pytest.mark.parametrize("form", range(len(FORMS)))
+def test_fit_forms_each_outer_iteration(cg, data, b, s, form):
+    kw = FORMS[form]
+    if kw.get("fused_variant") == 3 and s < 2:
+        pytest.skip("variant 3 needs s > 1")
+    p = data["logistic"]
+    X = cg.dense_matrix(_dev(p.X))
+    H = 4 if s * b >= 2048 else 6
+    local_check(cg, X, lambda idx: p.X[idx].astype(np.float64), p.y, 520, b, s, 0.5, 1e-4, 9, H,
+                what=f"b={b} s={s} {kw}", **kw)
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "f16", "fp8"])
+@pytest.mark.parametrize("b,s", [(32, 8), (64, 16), (128, 32)])
+def test_fit_low_precision_each_outer_iteration(cg, data, fmt, b, s):
+    p = data["logistic"]
+    X, keep = _stored(cg, p.X, fmt)
+    _, _, exact = R.quantize(p.X, fmt)
+    local_check(cg, X, lambda idx: exact[idx], p.y, 520, b, s, 0.5, 1e-4, 5, 4,
+                scaled=fmt == "fp8", what=f"{fmt} b={b} s={s}")
+
+
+@pytest.mark.parametrize("loss", ["linear", "poisson"])
+@pytest.mark.parametrize("b,s,kw", [(64, 16, {}), (32, 8, dict(exec_mode=2)),
+                                    (16, 4, dict(exec_mode=1, fused_variant=1)),
+                                    (128, 4, dict(exec_mode=1, fused_variant=2)),
+                                    (24, 5, {})])
+def test_glm_fit_each_outer_iteration(cg, data, loss, b, s, kw):
+    """Linear and Poisson losses (Sec. 2.1): only the residual formula of the
+    recurrence changes; every form, checked per outer iteration."""
+    p = data[loss]
+    X = cg.dense_matrix(_dev(p.X))
+    local_check(cg, X, lambda idx: p.X[idx].astype(np.float64), p.y, 520, b, s, ETA[loss], 1e-4,
+                13, 5, loss=loss, what=f"{loss} b={b} s={s} {kw}", **kw)
+
+
+# ------------------------------------------------------ the full-size workload
+
+@pytest.fixture(scope="module")
+def c2():
+    from workloads import dense_c2
+    return dense_c2(42, m=1 << 20, n=2048, m_test=1)
+
+
+@pytest.mark.parametrize("fmt,s", [("f32", 16), ("bf16", 16), ("fp8", 16), ("f32", 32),
+                                   ("bf16", 32)])
+def test_c2_full_size_each_outer_iteration(cg, c2, fmt, s):
+    """2^20 x 2048, b = 64, lambda = 1e-5, eta = 2, in the launch the benchmark
+    times (fused, automatic form and grid: at s = 32 the Gram units are
+    claimed dynamically): four outer iterations, each entry of x checked
+    against the oracle's outer iteration on the sampled rows."""
+    b, H, eta, lam, seed = 64, 4, 2.0, 1e-5, 42
+    X32 = torch.from_numpy(c2.X).cuda()
+    if fmt == "f32":
+        X = cg.dense_matrix(X32)
+        keep = X32
+
+        def exact_rows(idx):
+            return c2.X[idx].astype(np.float64)
+    else:
+        v, sc = cg.casgd_quantize(X32, {"bf16": cg.BF16, "fp8": cg.FP8E4M3}[fmt])
+        del X32
+        X = cg.dense_matrix(v, sc, n=2048)
+        keep = (v, sc)
+
+        def exact_rows(idx):
+            # per-row formats: quantising the sampled rows alone gives the
+            # stored values of those rows
+            return R.quantize(c2.X[idx], fmt)[2]
+    worst = local_check(cg, X, exact_rows, c2.y, 2048, b, s, eta, lam, seed, H,
+                        scaled=fmt == "fp8", what=f"c2 {fmt} s={s}")
+    print(f"\n[c2 local] {fmt} s={s}: max err/bound {worst:.3f}")
+    del keep

@@ -137,3 +137,23 @@ def test_csr_oracle_equals_dense_oracle(loss):
     assert np.linalg.norm(a - b) <= 1e-13 * np.linalg.norm(b)
     assert abs(R.loss_value_csr(p.row_ptr, p.col_idx, p.values, p.y, a, loss)
                - R.loss_value(D, p.y, a, loss)) < 1e-13
+
+
+@pytest.mark.parametrize("loss", ["logistic", "linear", "poisson"])
+def test_outer_rows_equals_sampled_outer_iteration(loss):
+    """The outer iteration on given rows is the sampled outer iteration with
+    the sampling and gather steps taken out: bitwise equal to casgd on the
+    rows that outer iteration samples, and its pieces equal outer_parts."""
+    p = dense_glm(3000, 48, 21, loss, var=1 / 48)
+    x = np.random.default_rng(4).standard_normal(48) * 0.1
+    b, s, eta, lam, seed, h = 8, 5, 0.3, 1e-3, 5, 7
+    idx = R.sample_indices(seed, h * s * b, s * b, p.X.shape[0])
+    o = R.outer_rows(p.X[idx], p.y[idx], x, eta, lam, b, s, loss=loss)
+    x1 = R.casgd(p.X, p.y, x, eta, lam, b, s, seed, h, 1, loss=loss)
+    assert np.array_equal(o["x"], x1)
+    parts = R.outer_parts(p.X, p.y, x, eta, lam, b, s, seed, h, loss=loss)
+    for k in ("r", "delta", "c"):
+        assert np.array_equal(o[k], parts[k])
+    low = np.tril(np.ones((s * b, s * b)), -1) * (np.arange(s * b)[:, None] // b
+                                                   > np.arange(s * b)[None, :] // b)
+    assert np.array_equal(o["G"] * low, parts["G"] * low)
