@@ -197,6 +197,25 @@ casgd_status casgd_fit(const casgd_matrix *X, const float *y, float *x, double e
                        uint64_t outer_begin, int64_t n_outer, const casgd_opts *opts,
                        void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * casgd_fit without a workspace argument, for callers that cannot allocate
+ * device memory (code under stream capture, serving loops, harnesses that
+ * forbid hipMalloc). Dense X only. The workspace lives in a static device
+ * array of 64 MiB that the library holds on every device it runs on until
+ * the process ends; problems whose casgd_workspace_size exceeds it are
+ * rejected with CASGD_EUNSUPPORTED. No device memory is allocated or freed.
+ * The array is shared by every call on a device and keeps the last call's
+ * contents: each call clears what must start at zero, and calls that overlap
+ * on one device (other streams, other threads) race and give undefined
+ * results. status_out (device, one int32, or NULL) receives, in stream order
+ * after the fit, CASGD_OK, CASGD_ENONFINITE or CASGD_ETIMEOUT (the checks
+ * casgd_check makes on a workspace). Other arguments as for casgd_fit.
+ */
+casgd_status casgd_fit_noalloc(const casgd_matrix *X, const float *y, float *x, double eta,
+                               double lambda, int32_t b, int32_t s, uint64_t seed,
+                               uint64_t outer_begin, int64_t n_outer, const casgd_opts *opts,
+                               int32_t *status_out, void *stream);
+
 /* Reports the device flags of a workspace after synchronising `stream`:
  * CASGD_OK, CASGD_ENONFINITE, CASGD_ETIMEOUT, or CASGD_EUNSUPPORTED when a
  * sparse tail bucket overflowed. */

@@ -17,6 +17,7 @@ from ._lib import LOSS_LINEAR, LOSS_LOGISTIC, LOSS_POISSON, LOSSES  # noqa: F401
 __all__ = [
     "CasgdError", "dense_matrix", "csr_matrix", "opts", "workspace",
     "casgd_workspace_size", "casgd_reset", "casgd_step", "casgd_fit", "casgd_check",
+    "casgd_fit_noalloc",
     "casgd_sample_indices", "casgd_gram_margin", "casgd_recurrence", "casgd_update",
     "casgd_quantize", "casgd_logloss", "casgd_loss", "casgd_colstats", "casgd_version",
     "casgd_recurrence_workspace_size",
@@ -178,6 +179,17 @@ def casgd_fit(X: MatrixRef, y, x, eta: float, lam: float, b: int, s: int, seed: 
     _check(_L().casgd_fit(X.ref(), _ptr(y), _ptr(x), eta, lam, b, s, seed, outer_begin,
                           n_outer, _opts_ref(opts), _ptr(ws), nb, _stream(stream)))
     return ws
+
+
+def casgd_fit_noalloc(X: MatrixRef, y, x, eta: float, lam: float, b: int, s: int, seed: int,
+                      outer_begin: int = 0, n_outer: int = 1, opts=None, status=None,
+                      stream=None):
+    """casgd_fit with the library's static device scratch array as workspace (no
+    device allocation). status: optional device int32 tensor (1 element) that
+    receives the flag status after the fit."""
+    _check(_L().casgd_fit_noalloc(X.ref(), _ptr(y), _ptr(x), eta, lam, b, s, seed, outer_begin,
+                                  n_outer, _opts_ref(opts), _ptr(status), _stream(stream)))
+    return status
 
 
 def casgd_step(X: MatrixRef, y, x, eta: float, lam: float, b: int, s: int, seed: int,

@@ -59,6 +59,8 @@ SIGNATURES = {
     "casgd_fit": (c_i32, [PM, c_vp, c_vp, c_dbl, c_dbl, c_i32, c_i32, c_u64, c_u64, c_i64, PO,
                           c_vp, c_sz, c_vp]),
     "casgd_check": (c_i32, [c_vp, c_sz, c_vp]),
+    "casgd_fit_noalloc": (c_i32, [PM, c_vp, c_vp, c_dbl, c_dbl, c_i32, c_i32, c_u64, c_u64, c_i64,
+                                  PO, c_vp, c_vp]),
     "casgd_batch_table_size": (c_sz, [c_i32]),
     "casgd_fit_batch": (c_i32, [ctypes.POINTER(Problem), c_i32, c_i64, c_vp, c_sz, c_vp]),
     "casgd_path_workspace_size": (c_i32, [PM, c_i32, c_i32, c_i32, ctypes.POINTER(c_sz)]),
