@@ -145,6 +145,58 @@ def gram_roofline(cg, X, n, b, s, dtype, reps=20):
             "paper_ai": round(paper_ai(b, s, n, DT_BYTES[dtype]), 1)}
 
 
+# Gram shapes of the roofline study: the dense 2^20 x 2048 workload at
+# s = 16, 32 (b = 64), the precision-sweep shape (4096 x 256, b = 128, s = 32)
+# and the paper's per-kernel roofline shape (Fig. 5: m = 8192, n = 16384,
+# b = 32, s = 32 .. 128).
+GRAM_SHAPES = [(1 << 20, 2048, 64, 16), (1 << 20, 2048, 64, 32), (4096, 256, 128, 32),
+               (8192, 16384, 32, 32), (8192, 16384, 32, 64), (8192, 16384, 32, 128)]
+
+
+def gram_shapes_bench(cg, dtypes, reps=10):
+    """Standalone Gram launches (casgd_gram_margin without margins: one
+    counter-clearing, one gather and one Gram launch per call) at the roofline
+    shapes, for each storage type. Timed with HIP events per call (gather
+    included); the Gram kernel alone is read from a kernel trace of this mode."""
+    import torch
+    stream = torch.cuda.current_stream()
+    rows = []
+    for (m, n, b, s) in GRAM_SHAPES:
+        g = torch.Generator(device="cuda")
+        g.manual_seed(m * 7 + n)
+        X32 = torch.randn(m, n, device="cuda", generator=g) * (1.0 / math.sqrt(n))
+        for dt in dtypes:
+            if dt == "f32":
+                X = cg.dense_matrix(X32)
+                keep = None
+            else:
+                keep = cg.casgd_quantize(X32, DT_NAME[dt])
+                X = cg.dense_matrix(keep[0], keep[1], n=n)
+            sb = s * b
+            G = torch.empty(sb, sb, device="cuda")
+            ws = cg.workspace(cg.casgd_workspace_size(X, b, s))
+            for h in range(2):
+                cg.casgd_gram_margin(X, None, b, s, SEED, h, G=G, ws=ws, stream=stream)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for h in range(reps):
+                cg.casgd_gram_margin(X, None, b, s, SEED, h, G=G, ws=ws, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / reps
+            fl = gram_flops(b, s, n)
+            rows.append({"m": m, "n": n, "b": b, "s": s, "storage": dt,
+                         "us_per_call_with_gather": round(us, 3),
+                         "gram_flops": fl, "paper_flops": 2.0 * sb * sb * n})
+            log(f"[gram] m={m} n={n} b={b} s={s} {dt}: {us:.2f} us per call "
+                f"({fl / (us * 1e-6) / 1e12:.1f} TFLOP/s incl. gather)")
+            del G, ws, X, keep
+        del X32
+        torch.cuda.empty_cache()
+    return {"metric": "standalone Gram launches at the roofline shapes", "rows": rows}
+
+
 def cpu_baseline(wl: Workload, b, s, eta, lam, budget_s=15.0):
     """The FP64 oracle (as it stands) on the host cores: outer iterations of the
     same workload until about `budget_s` seconds have been spent."""
@@ -533,6 +585,8 @@ def main():
                     help="run the autotuner on the dense workload and list its candidates")
     ap.add_argument("--c5-batch", action="store_true",
                     help="uneven problems at full size: batched vs one launch per problem")
+    ap.add_argument("--gram-shapes", action="store_true",
+                    help="standalone Gram launches at the roofline shapes (all storage types)")
     ap.add_argument("--c5-train", type=int, default=256)
     ap.add_argument("--c5-eval", type=int, default=64)
     args = ap.parse_args()
@@ -555,6 +609,9 @@ def main():
         return
     if args.c5:
         print(json.dumps(c5_bench(cg, args.c5_train, args.c5_eval)), flush=True)
+        return
+    if args.gram_shapes:
+        print(json.dumps(gram_shapes_bench(cg, ["f32", "bf16", "fp8"])), flush=True)
         return
     if args.c5_batch:
         H = args.steps if args.steps is not None else 32

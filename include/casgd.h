@@ -343,6 +343,74 @@ casgd_status casgd_update(const casgd_matrix *X, float *x, const float *c, int32
                           int32_t s, uint64_t seed, uint64_t outer_iter, double eta,
                           double lambda, void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------ precision selection */
+
+/*
+ * Thm. 5.1 (mixed-precision local error of one outer iteration) as a
+ * run-time precision selector. The theorem bounds the forward error of one
+ * outer iteration by nine additive terms E_slot = coef_slot * u_slot, one per
+ * precision slot (storage of X u_A, margin GEMV u_r, Gram GEMM u_G, inner
+ * corrections u_c, residual nonlinearity u_sigma, gradient GEMV u_g, weights
+ * u_x, and the two all-reduce slots, which vanish on one device), plus a
+ * remainder at most C_loc * Omega * sum E (C_loc = 2), valid while
+ * Omega <= 1/2. The coefficients depend on the sampled rows Y, x and the
+ * exact residual history d through ||Y||_2, K_s = ||(I - L_sigma alpha
+ * |G_L|)^-1||_2, ||H_L||_2 and the source quantities T_g, T_r, T_G, T_c.
+ * Constants: L_sigma = 1/4 (logistic), 1 (linear), exp(max z) over the block
+ * (Poisson); C_delta = 8; D_delta = 1 (logistic) or max |d| (linear,
+ * Poisson). Slots of this library: u_r = u_G = 2 u_A + gamma_n(u32) for
+ * low-precision storage (FP32 accumulation; gamma_n(u32) for FP32 storage),
+ * u_g = 2 u_A + gamma_sb(u32), u_sigma = u_c, u_x = u32. Nominal unit
+ * roundoffs: FP8-E4M3 2^-4, BF16 2^-8, FP16 2^-11, FP32 storage of an FP32
+ * master copy 0; corrections FP32 2^-24 or FP64 2^-53.
+ */
+enum { CASGD_SLOT_A = 0, CASGD_SLOT_R, CASGD_SLOT_G, CASGD_SLOT_C, CASGD_SLOT_SIGMA,
+       CASGD_SLOT_GRAD, CASGD_SLOT_X, CASGD_SLOTS };
+
+typedef struct {
+    int32_t dtype;        /* storage format of X (CASGD_F32 .. CASGD_FP8E4M3) */
+    int32_t recur_prec;   /* 32 or 64 (slot u_c) */
+    int32_t valid;        /* Omega <= 1/2 and (s-1) b u_c < 1 */
+    int32_t reserved;
+    double u[CASGD_SLOTS]; /* unit roundoff or Higham factor of each slot */
+    double E[CASGD_SLOTS]; /* the leading terms E_slot = coef_slot * u_slot */
+    double sum, Omega, bound, rel_bound;  /* bound = (1 + 2 Omega) sum; rel_bound = bound / ||x^(s)|| */
+} casgd_precision_candidate;
+
+typedef struct {
+    double alpha, norm_Y, K_s, norm_HL, T_g, T_r, T_G, T_c, norm_x_next, L_sigma, D_delta;
+    double coef[CASGD_SLOTS];
+    int32_t ncand;        /* candidates evaluated (storage formats x {FP32, FP64} corrections) */
+    int32_t chosen;       /* index into cand */
+    int32_t dtype;        /* the chosen storage format */
+    int32_t recur_prec;   /* the chosen correction precision (casgd_opts.recur_prec) */
+    int32_t meets_budget; /* 0: no valid candidate met rel_budget; the most accurate valid one is chosen */
+    int32_t reserved;
+    casgd_precision_candidate cand[8];
+} casgd_precision_report;
+
+/* Workspace bytes of casgd_select_precision (X dense FP32). */
+size_t casgd_precision_workspace_size(const casgd_matrix *X, int32_t b, int32_t s);
+
+/*
+ * Evaluate Thm. 5.1 on outer iteration `outer_iter` of (X, y, seed) from x
+ * (all device; X the FP32 master copy) with step eta (the theorem's setting
+ * has no L2 term, so lambda = 0) and the given loss, and choose the cheapest
+ * assignment -- storage FP8-E4M3, BF16, FP16, FP32 in that order (those set in
+ * the bit mask `allowed`, bit = dtype; 0 = all), corrections FP32 before
+ * FP64 -- whose relative bound bound / ||x^(s)|| is at most rel_budget and
+ * which is valid. FP16 is skipped when a sampled entry is outside its range.
+ * The gather, Gram, margins and exact residual history run on the GPU (ws,
+ * casgd_precision_workspace_size bytes); the norms and the selection run on
+ * the host in FP64. Synchronous (a planning call, not part of any fit).
+ * Fills out (host) with every candidate's terms and the choice.
+ */
+casgd_status casgd_select_precision(const casgd_matrix *X, const float *y, const float *x,
+                                    double eta, int32_t b, int32_t s, uint64_t seed,
+                                    uint64_t outer_iter, int32_t loss, double rel_budget,
+                                    uint32_t allowed, casgd_precision_report *out, void *ws,
+                                    size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------- storage formats */
 
 /*

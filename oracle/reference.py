@@ -494,7 +494,7 @@ def local_error_bound(Y, x, yI, b: int, s: int, eta: float, *, u_A: float,
                       gamma_r: float, gamma_G: float, u_c: float, u_sigma: float,
                       gamma_g: float, u_x: float, C_delta: float = 8.0,
                       D_delta: float = 1.0, L_sigma: float = 0.25,
-                      C_loc: float = 2.0) -> dict:
+                      C_loc: float = 2.0, loss="logistic") -> dict:
     """Local forward-error bound of one outer iteration (Thm. 5.1, P = 1).
 
     Y (sb x n, exact rows), x and yI are the exact inputs. With one device
@@ -514,7 +514,7 @@ def local_error_bound(Y, x, yI, b: int, s: int, eta: float, *, u_A: float,
     absY = np.abs(Y)
     HL = np.where(mask, absY @ absY.T, 0.0)
     r = Y @ x
-    d, _ = inner_corrections(GL, r, yI, b, s, eta, 0.0)
+    d, _ = inner_corrections(GL, r, yI, b, s, eta, 0.0, loss=loss)
     M = L_sigma * alpha * np.abs(GL)
     # Neumann series terminates: |G_L| is strictly block-lower, so M^s = 0.
     inv = np.eye(sb)
@@ -548,7 +548,8 @@ def local_error_bound(Y, x, yI, b: int, s: int, eta: float, *, u_A: float,
     tau = K_s * L_sigma * alpha * (2 * u_A + gamma_G) * float(np.linalg.norm(HL, 2))
     Omega = max(omega, tau)
     return dict(E=E, sum=total, Omega=Omega, K_s=K_s, bound=(1 + C_loc * Omega) * total,
-                x_exact=x_s)
+                x_exact=x_s, norm_Y=normY, norm_HL=float(np.linalg.norm(HL, 2)), T_g=T_g,
+                T_r=T_r, T_G=T_G, T_c=T_c, d=d)
 
 
 def uniform_precision_bound(Y, x, yI, b, s, eta, u, **kw) -> dict:

@@ -24,7 +24,7 @@ __all__ = [
     "casgd_path_workspace_size", "casgd_sparse_prepare", "casgd_fit_path",
     "casgd_fit_batch", "casgd_quantize_scaled", "casgd_mlp_features", "casgd_mlp_forward",
     "casgd_mlp_loss_grad", "casgd_mlp_backward", "casgd_adam_step", "casgd_hess_diag",
-    "MLP_PARAMS",
+    "casgd_select_precision", "MLP_PARAMS",
 ]
 
 MLP_PARAMS = 450
@@ -440,6 +440,32 @@ def casgd_loss(X: MatrixRef, y, xs, loss="logistic", stream=None):
     _check(_L().casgd_loss(X.ref(), _ptr(y), _ptr(xs2), count, xs2.stride(0), _loss_code(loss),
                            _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
     return out if xs.dim() == 2 else out[0]
+
+
+def casgd_select_precision(X: MatrixRef, y, x, eta: float, b: int, s: int, seed: int,
+                           outer_iter: int = 0, loss=0, rel_budget: float = 1e-6,
+                           allowed: int = 0, stream=None) -> dict:
+    """Thm. 5.1 evaluated on one sampled outer iteration (X: the FP32 master copy)
+    and the cheapest (storage, correction precision) within rel_budget.
+    Returns the report as a dict (slot terms keyed by name)."""
+    ws = workspace(int(_L().casgd_precision_workspace_size(X.ref(), b, s)))
+    rep = _lib.PrecisionReport()
+    _check(_L().casgd_select_precision(X.ref(), _ptr(y), _ptr(x), eta, b, s, seed, outer_iter,
+                                       _loss_code(loss), rel_budget, allowed, ctypes.byref(rep),
+                                       _ptr(ws), ws.numel(), _stream(stream)))
+    names = _lib.SLOT_NAMES
+    cands = []
+    for i in range(rep.ncand):
+        c = rep.cand[i]
+        cands.append(dict(dtype=c.dtype, recur_prec=c.recur_prec, valid=bool(c.valid),
+                          u=dict(zip(names, list(c.u))), E=dict(zip(names, list(c.E))),
+                          sum=c.sum, Omega=c.Omega, bound=c.bound, rel_bound=c.rel_bound))
+    return dict(alpha=rep.alpha, norm_Y=rep.norm_Y, K_s=rep.K_s, norm_HL=rep.norm_HL,
+                T_g=rep.T_g, T_r=rep.T_r, T_G=rep.T_G, T_c=rep.T_c,
+                norm_x_next=rep.norm_x_next, L_sigma=rep.L_sigma, D_delta=rep.D_delta,
+                coef=dict(zip(names, list(rep.coef))), candidates=cands, chosen=rep.chosen,
+                dtype=rep.dtype, recur_prec=rep.recur_prec,
+                meets_budget=bool(rep.meets_budget))
 
 
 def casgd_colstats(X: MatrixRef, stream=None):

@@ -44,6 +44,25 @@ class Problem(ctypes.Structure):
                 ("variant", c_i32), ("recur_prec", c_i32), ("loss", c_i32)]
 
 
+SLOTS = 7
+SLOT_NAMES = ["A", "r", "G", "c", "sigma", "g", "x"]
+
+
+class PrecisionCandidate(ctypes.Structure):
+    _fields_ = [("dtype", c_i32), ("recur_prec", c_i32), ("valid", c_i32), ("reserved", c_i32),
+                ("u", c_dbl * SLOTS), ("E", c_dbl * SLOTS), ("sum", c_dbl), ("Omega", c_dbl),
+                ("bound", c_dbl), ("rel_bound", c_dbl)]
+
+
+class PrecisionReport(ctypes.Structure):
+    _fields_ = [("alpha", c_dbl), ("norm_Y", c_dbl), ("K_s", c_dbl), ("norm_HL", c_dbl),
+                ("T_g", c_dbl), ("T_r", c_dbl), ("T_G", c_dbl), ("T_c", c_dbl),
+                ("norm_x_next", c_dbl), ("L_sigma", c_dbl), ("D_delta", c_dbl),
+                ("coef", c_dbl * SLOTS), ("ncand", c_i32), ("chosen", c_i32), ("dtype", c_i32),
+                ("recur_prec", c_i32), ("meets_budget", c_i32), ("reserved", c_i32),
+                ("cand", PrecisionCandidate * 8)]
+
+
 PM = ctypes.POINTER(Matrix)
 PO = ctypes.POINTER(Opts)
 
@@ -94,6 +113,10 @@ SIGNATURES = {
     "casgd_logloss_workspace_size": (c_sz, [c_i64]),
     "casgd_logloss": (c_i32, [PM, c_vp, c_vp, c_i64, c_i64, c_vp, c_vp, c_sz, c_vp]),
     "casgd_loss": (c_i32, [PM, c_vp, c_vp, c_i64, c_i64, c_i32, c_vp, c_vp, c_sz, c_vp]),
+    "casgd_precision_workspace_size": (c_sz, [PM, c_i32, c_i32]),
+    "casgd_select_precision": (c_i32, [PM, c_vp, c_vp, c_dbl, c_i32, c_i32, c_u64, c_u64, c_i32,
+                                       c_dbl, ctypes.c_uint32, ctypes.POINTER(PrecisionReport),
+                                       c_vp, c_sz, c_vp]),
     "casgd_colstats_workspace_size": (c_sz, [PM]),
     "casgd_colstats": (c_i32, [PM, c_vp, c_vp, c_sz, c_vp]),
 }

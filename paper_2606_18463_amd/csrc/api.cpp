@@ -41,7 +41,7 @@ int dtype_bytes(int dt) {
 }
 
 int dtype_vec(int dt) { return 16 / dtype_bytes(dt); }
-int slice_width_of(int dt) { return kLPR * dtype_vec(dt); }
+int slice_width_of(int dt) { return dtype_bytes(dt) ? kLPR * kEPL : 0; }
 
 int device_cus() {
     static int cached[64] = {0};
@@ -167,7 +167,7 @@ void dense_bind(const DenseLayout& L, void* ws, Dense* P) {
 
 // ----------------------------------------------------------- validation
 
-static casgd_status check_bs(int32_t b, int32_t s) {
+casgd_status check_bs(int32_t b, int32_t s) {
     if (b < 1 || s < 1) {
         set_error("b and s must be >= 1 (got b=%d, s=%d)", b, s);
         return CASGD_EINVAL;
@@ -179,7 +179,7 @@ static casgd_status check_bs(int32_t b, int32_t s) {
     return CASGD_OK;
 }
 
-static casgd_status check_dense(const casgd_matrix* X) {
+casgd_status check_dense(const casgd_matrix* X) {
     if (!X) {
         set_error("X is NULL");
         return CASGD_EINVAL;
@@ -254,7 +254,7 @@ static casgd_status check_scalars(double eta, double lambda) {
     return CASGD_OK;
 }
 
-static casgd_status check_ws(const void* ws, size_t ws_bytes, size_t need) {
+casgd_status check_ws(const void* ws, size_t ws_bytes, size_t need) {
     if (!ws) {
         set_error("workspace is NULL");
         return CASGD_EINVAL;
@@ -271,7 +271,7 @@ static casgd_status check_ws(const void* ws, size_t ws_bytes, size_t need) {
 }
 
 // Fill a Dense view for X, y, x and the scalars, bound to workspace ws.
-static casgd_status make_dense(const casgd_matrix* X, const float* y, float* x, double eta,
+casgd_status make_dense(const casgd_matrix* X, const float* y, float* x, double eta,
                                double lambda, int32_t b, int32_t s, uint64_t seed,
                                const casgd_opts* o, void* ws, size_t ws_bytes, Dense* P,
                                DenseLayout* L, bool need_ws) {

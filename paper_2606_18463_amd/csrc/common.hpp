@@ -49,12 +49,21 @@ template <> struct Store<DT_FP8> { using T = uint8_t;  static constexpr int kVec
 
 // OCP E4M3: sign, 4 exponent bits (bias 7), 3 mantissa bits; exponent field 0
 // is subnormal (m * 2^-9). Code 0x7f/0xff is NaN and never produced here.
-__device__ __forceinline__ float e4m3_to_float(uint32_t c) {
-    const uint32_t e = (c >> 3) & 15u, mnt = c & 7u;
-    float v = (e == 0) ? (float)mnt * 0.001953125f
-                       : __uint_as_float(((e + 120u) << 23) | (mnt << 20));
-    return (c & 0x80u) ? -v : v;
+// Decoded by gfx950's FP8 convert (OCP E4M3; every code is checked against the
+// oracle's table): byte `sel` of the word w.
+template <int SEL>
+__device__ __forceinline__ float e4m3_byte(uint32_t w) {
+    return __builtin_amdgcn_cvt_f32_fp8((int)w, SEL);
 }
+__device__ __forceinline__ float e4m3_sel(uint32_t w, int sel) {
+    switch (sel & 3) {
+        case 0: return e4m3_byte<0>(w);
+        case 1: return e4m3_byte<1>(w);
+        case 2: return e4m3_byte<2>(w);
+        default: return e4m3_byte<3>(w);
+    }
+}
+__device__ __forceinline__ float e4m3_to_float(uint32_t c) { return e4m3_byte<0>(c); }
 
 // Round to nearest, ties to even, saturating to +-448.
 __device__ __forceinline__ uint32_t float_to_e4m3(float v) {
@@ -112,8 +121,30 @@ __device__ __forceinline__ float v16_elem(const V16& v, int e) {
         const uint32_t w = v.w[e >> 1];
         return f16_to_float((e & 1) ? (w >> 16) : (w & 0xffffu));
     } else {
-        return e4m3_to_float((v.w[e >> 2] >> (8 * (e & 3))) & 0xffu);
+        return e4m3_sel(v.w[e >> 2], e & 3);
     }
+}
+
+// Load the EPL stored elements at p (EPL * sizeof(T) bytes, aligned to that
+// size) into the first words of a V16 (element e at the same place as in a
+// full 16-byte vector, so v16_elem reads it).
+template <int DT, int EPL>
+__device__ __forceinline__ V16 load_elems(const typename Store<DT>::T* p) {
+    using T = typename Store<DT>::T;
+    constexpr int BYTES = EPL * (int)sizeof(T);
+    static_assert(BYTES == 16 || BYTES == 8 || BYTES == 4, "4, 8 or 16 bytes per load");
+    V16 v;
+    if constexpr (BYTES == 16) {
+        const uint4 q = *reinterpret_cast<const uint4*>(p);
+        v.w[0] = q.x; v.w[1] = q.y; v.w[2] = q.z; v.w[3] = q.w;
+    } else if constexpr (BYTES == 8) {
+        const uint2 q = *reinterpret_cast<const uint2*>(p);
+        v.w[0] = q.x; v.w[1] = q.y; v.w[2] = 0u; v.w[3] = 0u;
+    } else {
+        v.w[0] = *reinterpret_cast<const uint32_t*>(p);
+        v.w[1] = v.w[2] = v.w[3] = 0u;
+    }
+    return v;
 }
 
 // Load kVec elements starting at element k of a row with n valid elements.

@@ -14,6 +14,7 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTile = 64;   // Gram tile edge in sampled rows
 constexpr int kLPR = 4;     // lanes per row in the update / margin passes
+constexpr int kEPL = 4;     // stored elements per lane and row in those passes
 constexpr int kNT = 256;    // threads per workgroup of the dense kernels
 constexpr int kNW = kNT / 64;
 
@@ -93,9 +94,11 @@ __host__ __device__ inline int recurrence_tpr(int NT, int b) {
     return t;
 }
 
-// Column-slice width of the update / margin passes for a storage type.
+// Column-slice width of the update / margin passes: kLPR lanes of kEPL
+// elements (16 columns for every storage type, so a narrower type gets as
+// many slices -- workgroups -- as FP32; its loads are 8 or 4 bytes).
 template <int DT>
-constexpr int slice_width() { return kLPR * Store<DT>::kVec; }
+constexpr int slice_width() { return kLPR * kEPL; }
 
 // ------------------------------------------------------------------ Gram
 // Tile p of the lower triangle (TJ >= TI) in row-major triangular order.
@@ -454,7 +457,7 @@ __device__ __forceinline__ void update_margin_slice(const Dense& P, int slice, c
                                     bool do_update, uint64_t hn, bool do_margin, float* rp_out,
                                     float* red, float* xs, int64_t snap_row) {
     using T = typename Store<DT>::T;
-    constexpr int VEC = Store<DT>::kVec;
+    constexpr int VEC = kEPL;
     constexpr int KW = slice_width<DT>();
     constexpr int RPW = kWave / kLPR;
     constexpr int U = 16;   // rows in flight per lane: 1024 rows per workgroup pass
@@ -485,8 +488,7 @@ __device__ __forceinline__ void update_margin_slice(const Dense& P, int slice, c
                 const int t = t0 + u * STRIDE;
                 const int tc = t < sbpad ? t : sbpad - 1;
                 const int tw = t < P.sb ? t : P.sb - 1;
-                const uint4 q = *reinterpret_cast<const uint4*>(Y + (int64_t)tc * P.ldy);
-                v[u].w[0] = q.x; v[u].w[1] = q.y; v[u].w[2] = q.z; v[u].w[3] = q.w;
+                v[u] = load_elems<DT, kEPL>(Y + (int64_t)tc * P.ldy);
                 const float cw = c[tw] * sI[tw];
                 ct[u] = t < P.sb ? cw : 0.f;
             }
@@ -537,8 +539,7 @@ __device__ __forceinline__ void update_margin_slice(const Dense& P, int slice, c
             for (int u = 0; u < U; ++u) {
                 const int t = t0 + u * STRIDE;
                 const int tc = t < sbpad ? t : sbpad - 1;
-                const uint4 q = *reinterpret_cast<const uint4*>(Y + (int64_t)tc * P.ldy);
-                v[u].w[0] = q.x; v[u].w[1] = q.y; v[u].w[2] = q.z; v[u].w[3] = q.w;
+                v[u] = load_elems<DT, kEPL>(Y + (int64_t)tc * P.ldy);
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {

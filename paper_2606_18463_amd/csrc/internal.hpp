@@ -60,6 +60,12 @@ casgd_status run_recurrence_multi(const Dense& P, const float* G, const float* r
                                   hipStream_t st);
 casgd_status run_update(const Dense& P, int dtype, const float* c, uint64_t h, hipStream_t st);
 casgd_status check_loss(int loss);
+casgd_status check_dense(const casgd_matrix* X);
+casgd_status check_bs(int32_t b, int32_t s);
+casgd_status check_ws(const void* ws, size_t ws_bytes, size_t need);
+casgd_status make_dense(const casgd_matrix* X, const float* y, float* x, double eta,
+                        double lambda, int32_t b, int32_t s, uint64_t seed, const casgd_opts* o,
+                        void* ws, size_t ws_bytes, Dense* P, DenseLayout* L, bool need_ws);
 casgd_status run_zero(unsigned* p, int64_t words, hipStream_t st);
 casgd_status run_fit_batch(const Dense* table_dev, const int2* wgmap_dev, int grid, int dtype,
                            size_t lds, unsigned long long spin, hipStream_t st);

@@ -142,3 +142,32 @@ def test_one_outer_iteration_within_theorem_bound_bounded_entries(cg, c1, fmt, b
     print(f"\n[thm5.1 bounded] fmt={fmt} b={b} s={s} u_A={u_A:.2e} error={err:.3e} "
           f"bound={res['bound']:.3e} ratio={err / res['bound']:.3f}")
     assert err <= res["bound"]
+
+
+def test_fp8_decode_every_code(cg):
+    """Every finite OCP E4M3 code decodes (hardware convert) to the oracle's
+    value; the NaN codes 0x7f and 0xff decode to NaN. Two rows of the 256
+    codes with unit scales: the column means are the decoded values; a
+    weight vector picks them up through the margin and update passes too."""
+    codes = np.tile(np.arange(256, dtype=np.uint8), (2, 1))
+    Xd = torch.from_numpy(codes).cuda()
+    X = cg.dense_matrix(Xd, torch.ones(2, device="cuda"), n=256)
+    stats = cg.casgd_colstats(X).cpu().numpy().astype(np.float64)
+    want = R.e4m3_decode(np.arange(256, dtype=np.uint8))
+    nan = np.isin(np.arange(256), [0x7F, 0xFF])
+    assert np.array_equal(stats[~nan, 0], want[~nan])
+    assert np.all(np.isnan(stats[nan, 0]))
+    # the update pass: one s = 1 step from x = 0 with eta = b gives
+    # x = sum_t c_t * row_t with c_t = y_t / 2 (logistic residual at z = 0)
+    fin = codes[:, ~nan].copy()
+    n = fin.shape[1]
+    ld = (n + 15) // 16 * 16
+    pad = np.zeros((2, ld), np.uint8)
+    pad[:, :n] = fin
+    X2 = cg.dense_matrix(torch.from_numpy(pad).cuda(), torch.ones(2, device="cuda"), n=n)
+    x = torch.zeros(n, device="cuda")
+    y = torch.ones(2, device="cuda")
+    ws = cg.casgd_fit(X2, y, x, 1.0, 0.0, 1, 1, 3, 0, 1)
+    cg.casgd_check(ws)
+    row = R.e4m3_decode(fin[0])
+    assert np.array_equal(x.cpu().numpy().astype(np.float64), 0.5 * row)
