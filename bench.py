@@ -197,6 +197,47 @@ def gram_shapes_bench(cg, dtypes, reps=10):
     return {"metric": "standalone Gram launches at the roofline shapes", "rows": rows}
 
 
+def e2e_study(cg, H: int = 320_000, snaps: int = 64):
+    """Error study of the precision recipes on the 4096 x 256 workload
+    (logistic, b = 32, s = 16, eta = 0.1, lambda = 0, the paper's long-horizon
+    setting): FP32 everywhere; BF16 and FP16 storage with FP32 elsewhere (the
+    mixed recipes); and the end-to-end BF16 and FP16 baselines (every slot
+    rounded to the format). Relative test-loss gap to the FP32 run at every
+    snapshot."""
+    import torch
+    from workloads import dense_c1
+    p = dense_c1(SEED)
+    b, s, eta, lam = 32, 16, 0.1, 0.0
+    Xt = cg.dense_matrix(torch.from_numpy(p.X_test.astype(np.float32)).cuda())
+    yt = torch.from_numpy(p.y_test.astype(np.float32)).cuda()
+    y = torch.from_numpy(p.y.astype(np.float32)).cuda()
+    X32 = torch.from_numpy(p.X.astype(np.float32)).cuda()
+    every = H // snaps
+    out = {}
+    for name, dt, e2e in (("fp32", cg.F32, 0), ("bf16 storage", cg.BF16, 0),
+                          ("fp16 storage", cg.F16, 0), ("e2e fp16", cg.F16, 2),
+                          ("e2e bf16", cg.BF16, 1)):
+        v, sc = cg.casgd_quantize(X32, dt)
+        X = cg.dense_matrix(v, sc, n=256)
+        hist = torch.zeros(snaps, 256, device="cuda")
+        x = torch.zeros(256, device="cuda")
+        o = cg.opts(snapshot_every=every, x_history=hist, e2e=e2e)
+        t0 = time.perf_counter()
+        ws = cg.casgd_fit(X, y, x, eta, lam, b, s, SEED, 0, snaps * every, opts=o)
+        torch.cuda.synchronize()
+        cg.casgd_check(ws)
+        out[name] = cg.casgd_logloss(Xt, yt, hist).cpu().numpy()
+        log(f"[e2e-study] {name}: {time.perf_counter() - t0:.1f}s, final test loss "
+            f"{out[name][-1]:.8f}")
+    ref = out["fp32"]
+    rows = {k: {"final_rel_gap": float(abs(v[-1] - ref[-1]) / ref[-1]),
+                "max_rel_gap": float(np.max(np.abs(v - ref) / ref)),
+                "final_test_loss": float(v[-1])} for k, v in out.items()}
+    return {"metric": "relative test-loss gap to FP32 (precision recipes)",
+            "workload": "dense 4096x256 logistic (N(0,1/256)), b=32, s=16, eta=0.1, lambda=0",
+            "outer_iterations": snaps * every, "snapshots": snaps, "recipes": rows}
+
+
 def cpu_baseline(wl: Workload, b, s, eta, lam, budget_s=15.0):
     """The FP64 oracle (as it stands) on the host cores: outer iterations of the
     same workload until about `budget_s` seconds have been spent."""
@@ -587,6 +628,8 @@ def main():
                     help="uneven problems at full size: batched vs one launch per problem")
     ap.add_argument("--gram-shapes", action="store_true",
                     help="standalone Gram launches at the roofline shapes (all storage types)")
+    ap.add_argument("--e2e-study", action="store_true",
+                    help="long-horizon test-loss gap of the precision recipes to FP32")
     ap.add_argument("--c5-train", type=int, default=256)
     ap.add_argument("--c5-eval", type=int, default=64)
     args = ap.parse_args()
@@ -609,6 +652,10 @@ def main():
         return
     if args.c5:
         print(json.dumps(c5_bench(cg, args.c5_train, args.c5_eval)), flush=True)
+        return
+    if args.e2e_study:
+        H = args.steps if args.steps is not None else 320_000
+        print(json.dumps(e2e_study(cg, H)), flush=True)
         return
     if args.gram_shapes:
         print(json.dumps(gram_shapes_bench(cg, ["f32", "bf16", "fp8"])), flush=True)

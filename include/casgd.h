@@ -162,6 +162,16 @@ typedef struct {
     int32_t rec_split;
     /* CASGD_LOSS_* (0 = logistic). */
     int32_t loss;
+    /* End-to-end low-precision baseline (the paper's all-BF16 and all-FP16
+     * recipes, Table 3 columns I and H; dense X only): 0 = off, 1 = BF16
+     * (X stored in BF16), 2 = FP16 (X stored in FP16). Every slot's output is
+     * rounded to the format, round to nearest even: G, r, the correction sum
+     * a_j, z_j = fl(beta^j r_j + alpha a_j), delta_j, c_j, the gradient
+     * g = Y^T c and x <- fl(beta^s x + alpha g); sums inside a kernel
+     * accumulate in FP32 (CDNA has no FP16-accumulate matrix instruction, so
+     * the FP16 recipe's accumulate-in-FP16 slots are not emulated). The
+     * corrections run in FP32 (recur_prec 64 is rejected). */
+    int32_t e2e;
 } casgd_opts;
 
 const char *casgd_status_string(casgd_status st);

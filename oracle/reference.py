@@ -470,6 +470,64 @@ def quantize(X32: np.ndarray, fmt: str):
     raise ValueError(fmt)
 
 
+def round_to_format(v, fmt: str | None) -> np.ndarray:
+    """Round FP64 values to BF16 or FP16 (round to nearest, ties to even,
+    subnormals of the format included; FP16 overflows to +-inf); fmt None
+    returns the values unchanged."""
+    v = np.asarray(v, dtype=np.float64)
+    if fmt is None:
+        return v.copy()
+    p, emin = {"bf16": (8, -126), "f16": (11, -14)}[fmt]
+    _, e = np.frexp(v)
+    q = np.maximum(e - p, emin - p + 1)              # quantum exponent at v's binade
+    r = np.ldexp(np.rint(np.ldexp(v, -q)), q)
+    if fmt == "f16":
+        r = np.where(np.abs(r) > 65504.0, np.copysign(np.inf, r), r)
+    return r
+
+
+def casgd_e2e(X, y, x0, eta: float, lam: float, b: int, s: int, seed: int, outer0: int,
+              nouter: int, fmt: str | None, loss="logistic", snapshots: bool = False):
+    """End-to-end low-precision s-step SGD (the paper's all-BF16 / all-FP16
+    recipes, Table 3): Algorithm 1 with every slot's output rounded to `fmt`
+    (round_to_format), sums exact in FP64 before the rounding:
+        G = fl(Y Y^T) (strict block-lower), r = fl(Y x),
+        a_j = fl(sum_{i<j} beta^(j-1-i) G_{j,i} delta_i), z_j = fl(beta^j r_j + alpha a_j),
+        delta_j = fl(delta(z_j, y_j)), c_j = fl(beta^(s-1-j) delta_j),
+        g = fl(Y^T c), x <- fl(beta^s x + alpha g).
+    X holds the exact stored values. Returns x (and the list of iterates after
+    every outer iteration when snapshots)."""
+    Xr = _f64(X)
+    yv = _f64(y)
+    x = round_to_format(_f64(x0), fmt)
+    m = Xr.shape[0]
+    alpha, beta = eta / b, 1.0 - eta * lam
+    lc = _loss_code(loss)
+    sb = s * b
+    snaps = []
+    for h in range(outer0, outer0 + nouter):
+        idx = sample_indices(seed, h * sb, sb, m)
+        Y, yI = Xr[idx], yv[idx]
+        G = round_to_format(Y @ Y.T, fmt)
+        r = round_to_format(Y @ x, fmt)
+        d = np.zeros(sb)
+        for j in range(s):
+            rows = slice(j * b, (j + 1) * b)
+            a = np.zeros(b)
+            for i in range(j):
+                a += beta ** (j - 1 - i) * (G[rows, i * b:(i + 1) * b] @ d[i * b:(i + 1) * b])
+            a = round_to_format(a, fmt)
+            z = round_to_format(beta ** j * r[rows] + alpha * a, fmt)
+            d[rows] = round_to_format([delta(float(zz), float(yy), lc)
+                                       for zz, yy in zip(z, yI[rows])], fmt)
+        c = round_to_format(np.repeat(beta ** (s - 1 - np.arange(s)), b) * d, fmt)
+        g = round_to_format(Y.T @ c, fmt)
+        x = round_to_format(beta ** s * x + alpha * g, fmt)
+        if snapshots:
+            snaps.append(x.copy())
+    return (x, snaps) if snapshots else x
+
+
 def unit_roundoff(fmt: str) -> float:
     return {"f64": U_FP64, "f32": U_FP32, "bf16": U_BF16, "f16": U_FP16,
             "fp8": U_E4M3}[fmt]

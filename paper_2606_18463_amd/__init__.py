@@ -123,15 +123,15 @@ def _loss_code(loss) -> int:
 
 def opts(recur_prec: int = 0, exec_mode: int = 0, snapshot_every: int = 0, x_history=None,
          t_history=None, spin_limit: int = 0, fused_variant: int = 0, grid_blocks: int = 0,
-         phase_trace=None, rec_split: int = 0, loss=0):
+         phase_trace=None, rec_split: int = 0, loss=0, e2e: int = 0):
     """casgd_opts; phase_trace: device int64 tensor of 8 words per traced outer iteration;
-    loss: "logistic", "linear", "poisson" or its code."""
+    loss: "logistic", "linear", "poisson" or its code; e2e: 0, 1 (BF16), 2 (FP16)."""
     o = _lib.Opts(recur_prec=recur_prec, exec_mode=exec_mode, snapshot_every=snapshot_every,
                   x_history=_ptr(x_history), t_history=_ptr(t_history), spin_limit=spin_limit,
                   fused_variant=fused_variant, grid_blocks=grid_blocks,
                   phase_trace=_ptr(phase_trace),
                   phase_trace_outer=0 if phase_trace is None else phase_trace.numel() // 8,
-                  rec_split=rec_split, loss=_loss_code(loss))
+                  rec_split=rec_split, loss=_loss_code(loss), e2e=e2e)
     o._keep = (x_history, t_history, phase_trace)
     return o
 

@@ -34,7 +34,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("recur_prec", c_i32), ("exec_mode", c_i32), ("snapshot_every", c_i64),
                 ("x_history", c_vp), ("t_history", c_vp), ("spin_limit", c_i64),
                 ("fused_variant", c_i32), ("grid_blocks", c_i32), ("phase_trace", c_vp),
-                ("phase_trace_outer", c_i64), ("rec_split", c_i32), ("loss", c_i32)]
+                ("phase_trace_outer", c_i64), ("rec_split", c_i32), ("loss", c_i32), ("e2e", c_i32)]
 
 
 class Problem(ctypes.Structure):

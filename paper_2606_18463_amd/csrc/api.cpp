@@ -309,6 +309,23 @@ casgd_status make_dense(const casgd_matrix* X, const float* y, float* x, double 
     }
     P->loss = o ? o->loss : CASGD_LOSS_LOGISTIC;
     if ((rc = check_loss(P->loss)) != CASGD_OK) return rc;
+    P->e2e = o ? o->e2e : 0;
+    if (P->e2e != 0) {
+        const int want = P->e2e == 1 ? CASGD_BF16 : CASGD_F16;
+        if (P->e2e != 1 && P->e2e != 2) {
+            set_error("e2e must be 0, 1 (BF16) or 2 (FP16), got %d", P->e2e);
+            return CASGD_EINVAL;
+        }
+        if (X->dtype != want) {
+            set_error("e2e %s needs X stored in %s", P->e2e == 1 ? "BF16" : "FP16",
+                      P->e2e == 1 ? "BF16" : "FP16");
+            return CASGD_EINVAL;
+        }
+        if (o->recur_prec == 64) {
+            set_error("e2e runs the corrections in FP32 (recur_prec 64 not allowed)");
+            return CASGD_EINVAL;
+        }
+    }
     if (o && o->snapshot_every > 0) {
         if (!o->x_history) {
             set_error("snapshot_every > 0 needs x_history");

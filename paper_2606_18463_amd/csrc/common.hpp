@@ -107,6 +107,21 @@ __device__ __forceinline__ uint32_t float_to_f16(float v) {
     return hb;
 }
 
+// End-to-end low-precision emulation (the paper's all-BF16 and all-FP16
+// baselines): every slot's output -- Gram entries, margins, the inner
+// correction sums, margins z, residuals, weights c, the gradient and the
+// iterate -- is rounded to the format (round to nearest even); sums inside a
+// kernel accumulate in FP32.
+enum : int { E2E_OFF = 0, E2E_BF16 = 1, E2E_F16 = 2 };
+__device__ __forceinline__ float e2e_round(float v, int mode) {
+    if (mode == E2E_BF16) return bf16_to_float(float_to_bf16(v));
+    if (mode == E2E_F16) return f16_to_float(float_to_f16(v));
+    return v;
+}
+__device__ __forceinline__ double e2e_round(double v, int mode) {
+    return mode == E2E_OFF ? v : (double)e2e_round((float)v, mode);
+}
+
 // A 16-byte vector of stored elements and its conversion to FP32.
 struct V16 { uint32_t w[4]; };
 

@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kNT) void k_margin_reduce(Dense P, const float* rp,
     if (t >= P.sb) return;
     float r = 0.f;
     for (int sl = 0; sl < P.nslices; ++sl) r += rp[(int64_t)sl * P.sb + t];
-    r_out[t] = r * pick3(P.sI, slot_of(h))[t];
+    r_out[t] = e2e_round(r * pick3(P.sI, slot_of(h))[t], P.e2e);
 }
 
 template <typename ACC>
@@ -316,7 +316,7 @@ casgd_status plan_fit(const Dense& P, int dtype, const casgd_opts* o, int64_t H,
         set_error("recur_prec must be 0, 32 or 64 (got %d)", prec);
         return CASGD_EINVAL;
     }
-    plan->recur64 = prec == 64 || (prec == 0 && sb >= 512);
+    plan->recur64 = P.e2e == 0 && (prec == 64 || (prec == 0 && sb >= 512));
     plan->exec_mode = (o && o->exec_mode) ? o->exec_mode : 1;
     if (plan->exec_mode != 1 && plan->exec_mode != 2) {
         set_error("exec_mode must be 0, 1 or 2 (got %d)", plan->exec_mode);

@@ -63,6 +63,7 @@ struct Dense {
     int recur64;            // FP64 recurrence
     int tpr;                // threads per row of the recurrence
     int loss;               // LOSS_* (residual formula of the recurrence)
+    int e2e;                // E2E_* end-to-end low-precision emulation
 };
 
 __device__ __forceinline__ int slot_of(uint64_t h) { return (int)(h % 3ull); }
@@ -386,7 +387,7 @@ __device__ __forceinline__ void gram_unit(const Dense& P, float* Gout, uint64_t 
             const int t = row0 + 16 * a + 4 * lg + v;
             if (t < P.sb && u < P.sb && bu < t / P.b) {
                 const float sr = P.scale ? sI[t] : 1.0f;
-                Gout[(int64_t)t * P.ldg + u] = part[a][v] * sr * sc;
+                Gout[(int64_t)t * P.ldg + u] = e2e_round(part[a][v] * sr * sc, P.e2e);
             }
         }
     }
@@ -513,7 +514,7 @@ __device__ __forceinline__ void update_margin_slice(const Dense& P, int slice, c
                 float g = 0.f;
 #pragma unroll
                 for (int ww = 0; ww < NW; ++ww) g += red[ww * KW + q];
-                xn = P.beta_s * P.x[k] + P.alpha * g;
+                xn = e2e_round(P.beta_s * P.x[k] + P.alpha * e2e_round(g, P.e2e), P.e2e);
                 P.x[k] = xn;
                 if (!isfinite(xn)) raise_flag(P.flags, FLAG_NONFINITE);
                 if (snap_row >= 0) P.x_hist[snap_row * P.n + k] = xn;
@@ -649,14 +650,14 @@ __device__ __forceinline__ void recurrence(const Dense& P, const float* G, const
                     r = (ACC)r_in[t];
                     yv = (ACC)y_in[t];
                 } else {
-                    r = rr * (ACC)pick3(P.sI, slot)[t];
+                    r = e2e_round(rr * (ACC)pick3(P.sI, slot)[t], P.e2e);
                     yv = (ACC)pick3(P.yI, slot)[t];
                 }
-                const ACC z = pw[j] * r + alpha * acc;
-                const ACC d = glm_delta<ACC>(z, yv, P.loss);
+                const ACC z = e2e_round(pw[j] * r + alpha * e2e_round(acc, P.e2e), P.e2e);
+                const ACC d = e2e_round(glm_delta<ACC>(z, yv, P.loss), P.e2e);
                 if (!isfinite(z) || !isfinite(d)) raise_flag(P.flags, FLAG_NONFINITE);
                 dl[t] = d;
-                c[t] = (float)(pw[s - 1 - j] * d);
+                c[t] = (float)e2e_round(pw[s - 1 - j] * d, P.e2e);
                 if (delta_out) delta_out[t] = (float)d;
             }
         }

@@ -31,7 +31,7 @@ __device__ __forceinline__ void reduce_margins(const Dense& P, const float* rp, 
         a += shfl_xor(a, 1);
         a += shfl_xor(a, 2);
         a += shfl_xor(a, 4);
-        if (e == 0) r_out[t] = a * sI[t];
+        if (e == 0) r_out[t] = e2e_round(a * sI[t], P.e2e);
     }
 }
 

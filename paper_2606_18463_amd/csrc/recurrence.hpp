@@ -193,11 +193,12 @@ __device__ void recurrence_multi(const Dense& P, const float* G, const float* r,
                 if (sub == 0 && q < b) {
                     const int t = j * b + q;
                     const ACC rv = (ACC)ry[p].x, yv = (ACC)ry[p].y;
-                    const ACC z = pw[j] * rv + alpha * (far + nsum);
-                    const ACC d = glm_delta<ACC>(z, yv, P.loss);
+                    const ACC z = e2e_round(pw[j] * rv + alpha * e2e_round(far + nsum, P.e2e),
+                                            P.e2e);
+                    const ACC d = e2e_round(glm_delta<ACC>(z, yv, P.loss), P.e2e);
                     if (!isfinite(z) || !isfinite(d)) raise_flag(P.flags, FLAG_NONFINITE);
                     dl[t] = d;
-                    c[t] = (float)(pw[s - 1 - j] * d);
+                    c[t] = (float)e2e_round(pw[s - 1 - j] * d, P.e2e);
                     if (delta_out) delta_out[t] = (float)d;
                     if (j < R) pub_put(dpub + (size_t)t * PW, d);
                 }

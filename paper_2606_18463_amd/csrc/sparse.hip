@@ -384,6 +384,10 @@ casgd_status sparse_fit(const casgd_matrix* X, const float* y, float* x_lanes,
     S.flags = at<unsigned>(ws, SL.off_flags);
     S.loss = opts ? opts->loss : 0;
     if ((rc = check_loss(S.loss)) != CASGD_OK) return rc;
+    if (opts && opts->e2e) {
+        set_error("the end-to-end low-precision emulation needs a dense X");
+        return CASGD_EUNSUPPORTED;
+    }
     for (int k = 0; k < 3; ++k) {
         S.Yh[k] = at<float>(ws, SL.off_Yh[k]);
         S.tcol[k] = at<int32_t>(ws, SL.off_tcol[k]);

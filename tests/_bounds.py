@@ -37,11 +37,13 @@ def _delta_lipschitz_and_eval(z, ez, yI, loss, u):
     return np.full_like(z, 0.25), u * (6.0 + np.abs(z)) * np.abs(d)
 
 
-def recurrence_bound(G, r, yI, delta, b, s, eta, lam, loss, e_r, e_G, u_acc):
+def recurrence_bound(G, r, yI, delta, b, s, eta, lam, loss, e_r, e_G, u_acc, u_round=0.0):
     """Bounds on |delta~ - delta| and |c~ - c| for corrections computed in
     unit roundoff u_acc from inputs within e_r (margins) and e_G (Gram,
     entrywise) of the exact r and G, against the exact corrections delta of
-    G, r, yI. Outputs are rounded to FP32 (included)."""
+    G, r, yI. Outputs are rounded to FP32 (included); u_round > 0 adds a
+    rounding (possibly flipped: 2 u_round relative) of the correction sum, of
+    z, of delta and of c to a format of that unit roundoff."""
     sb = s * b
     alpha, beta = eta / b, 1.0 - eta * lam
     A = np.abs(G)
@@ -59,35 +61,40 @@ def recurrence_bound(G, r, yI, delta, b, s, eta, lam, loss, e_r, e_G, u_acc):
             mag = mag + alpha * ((A[rows, cols] + e_G[rows, cols]) @ (w * (D[cols] + ed[cols])))
             ez = ez + alpha * (e_G[rows, cols] @ (w * (D[cols] + ed[cols]))
                                + A[rows, cols] @ (w * ed[cols]))
-        ez = ez + gamma(j * b + 4, u_acc) * mag
-        lip, ev = _delta_lipschitz_and_eval(zj, ez, yI[rows], loss, u_acc)
-        ed[rows] = lip * ez + ev
+        ez = ez + gamma(j * b + 4, u_acc) * mag + 2 * u_round * (np.abs(zj) + 2 * mag)
+        lip, ev = _delta_lipschitz_and_eval(zj, ez, yI[rows], loss, max(u_acc, u_round))
+        ed[rows] = lip * ez + ev + 2 * u_round * (D[rows] + lip * ez)
     pw = np.repeat(beta ** (s - 1 - np.arange(s, dtype=np.float64)), b)
     c = pw * delta
-    ec = pw * ed + (U32 + (s + 2) * u_acc) * (np.abs(c) + pw * ed)
+    ec = pw * ed + (U32 + (s + 2) * u_acc + 2 * u_round) * (np.abs(c) + pw * ed)
     ed_out = ed + U32 * (D + ed)
     return ed_out, ec
 
 
 def outer_bound(Y, x, yI, b, s, eta, lam, loss="logistic", u_acc=U64, scaled=False,
-                safety=1.5):
+                safety=1.5, u_round=0.0):
     """Entrywise bound on |x_new~ - x_new| for one outer iteration from x,
     computed on the GPU from the exact stored rows Y (sb x n): margins and
     Gram accumulated in FP32 (row scales applied in FP32 when `scaled`),
     corrections in unit roundoff u_acc, update accumulated in FP32. Returns
-    (bound, oracle pieces of R.outer_rows)."""
+    (bound, oracle pieces of R.outer_rows). u_round > 0 adds one rounding to
+    a format of that unit roundoff at every slot's output (in both of two
+    computations being compared: a rounding may flip by one unit in the last
+    place, 2 u_round relative)."""
     sb, n = Y.shape
     ex = R.outer_rows(Y, yI, x, eta, lam, b, s, loss=loss)
     aY = np.abs(Y)
     k = 2 if scaled else 1
-    e_r = 2 * gamma(n + 2 * k, U32) * (aY @ np.abs(x))
-    e_G = 2 * gamma(n + 2 * k, U32) * (aY @ aY.T)
+    e_r = 2 * gamma(n + 2 * k, U32) * (aY @ np.abs(x)) + 2 * u_round * np.abs(ex["r"])
+    e_G = 2 * gamma(n + 2 * k, U32) * (aY @ aY.T) + 2 * u_round * np.abs(ex["G"])
     _, ec = recurrence_bound(ex["G"], ex["r"], np.asarray(yI, np.float64), ex["delta"], b, s,
-                             eta, lam, loss, e_r, e_G, u_acc)
+                             eta, lam, loss, e_r, e_G, u_acc, u_round)
     alpha, beta = eta / b, 1.0 - eta * lam
     c = np.abs(ex["c"])
-    bound = alpha * (aY.T @ ec) + alpha * 2 * gamma(sb + 2 + k, U32) * (aY.T @ (c + ec)) \
-        + 4 * U32 * np.abs(ex["x"]) + 2 * U32 * beta ** s * np.abs(x) + 1e-30
+    g = aY.T @ (c + ec)
+    bound = alpha * (aY.T @ ec) + alpha * 2 * gamma(sb + 2 + k, U32) * g \
+        + 4 * U32 * np.abs(ex["x"]) + 2 * U32 * beta ** s * np.abs(x) + 1e-30 \
+        + 2 * u_round * (alpha * g + np.abs(ex["x"]) + alpha * (aY.T @ ec))
     return safety * bound, ex
 
 
