@@ -139,7 +139,7 @@ typedef struct {
      *   compute the next outer iteration's Gram (two barriers);
      * fused_variant 3 = the multi-workgroup recurrence (chain + helpers, as
      *   in exec_mode 2) runs while the other workgroups compute the next
-     *   Gram; two grid barriers (b = 16, 32, 64, 128; not in casgd_fit_batch);
+     *   Gram; two grid barriers (b = 16, 32, 64, 128);
      * grid_blocks = number of workgroups of the fused launch (capped at the
      *   number that can be resident). */
     int32_t fused_variant;
@@ -290,6 +290,11 @@ typedef struct {
     int32_t variant;
     int32_t recur_prec;
     int32_t loss;        /* CASGD_LOSS_* */
+    /* snapshots of this problem, as casgd_opts.snapshot_every / x_history /
+     * t_history (0 / NULL = none); the device clock is this problem's own */
+    int64_t snapshot_every;
+    float *x_history;
+    int64_t *t_history;
 } casgd_problem;
 
 /* Bytes of the device table workspace of a batch of `count` problems. */
@@ -299,12 +304,17 @@ size_t casgd_batch_table_size(int32_t count);
  * Fit `count` independent dense problems (probs: host array) in one
  * cooperative launch: each problem runs its whole fit (all of its outer
  * iterations, as casgd_fit would) on its own group of workgroups with its own
- * grid barrier, so short and long problems proceed concurrently. The problem
+ * grid barrier, so short and long problems proceed concurrently. Problems
+ * whose automatic form is fused variant 3 keep it when every problem's
+ * recurrence group fits on the device at once; otherwise those with the
+ * smallest modelled gain fall back to variant 2. On success the workgroups
+ * and the fused variant each problem runs with are written back to its
+ * `groups` and `variant` fields. The problem
  * table is uploaded to `table` (device, casgd_batch_table_size bytes) with a
  * synchronous copy before the launch. spin_limit as in casgd_opts (0 =
  * default). Results equal casgd_fit per problem for the same variant.
  */
-casgd_status casgd_fit_batch(const casgd_problem *probs, int32_t count, int64_t spin_limit,
+casgd_status casgd_fit_batch(casgd_problem *probs, int32_t count, int64_t spin_limit,
                              void *table, size_t table_bytes, void *stream);
 
 /* ------------------------------------------------- pieces of the iteration */

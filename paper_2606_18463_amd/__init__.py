@@ -228,7 +228,8 @@ def casgd_fit_path(X: MatrixRef, y, x_lanes, lambdas, eta: float, b: int, s: int
 def casgd_fit_batch(problems, spin_limit: int = 0, stream=None):
     """Fit many dense problems in one launch. `problems`: list of dicts with keys
     X (MatrixRef), y, x, eta, lam, b, s, seed and optionally outer_begin,
-    n_outer, ws, groups, variant, recur_prec, loss. Returns the list of workspaces."""
+    n_outer, ws, groups, variant, recur_prec, loss, snapshot_every, x_history,
+    t_history. Returns the list of workspaces."""
     n = len(problems)
     arr = (_lib.Problem * n)()
     keep = []
@@ -243,9 +244,15 @@ def casgd_fit_batch(problems, spin_limit: int = 0, stream=None):
                               outer_begin=q.get("outer_begin", 0), n_outer=q.get("n_outer", 1),
                               ws=_ptr(ws), ws_bytes=ws.numel(), groups=q.get("groups", 0),
                               variant=q.get("variant", 0), recur_prec=q.get("recur_prec", 0),
-                              loss=_loss_code(q.get("loss", 0)))
+                              loss=_loss_code(q.get("loss", 0)),
+                              snapshot_every=q.get("snapshot_every", 0),
+                              x_history=_ptr(q.get("x_history")),
+                              t_history=_ptr(q.get("t_history")))
     tb = workspace(int(_L().casgd_batch_table_size(n)))
     _check(_L().casgd_fit_batch(arr, n, spin_limit, _ptr(tb), tb.numel(), _stream(stream)))
+    for i, q in enumerate(problems):
+        q["groups_used"] = int(arr[i].groups)
+        q["variant_used"] = int(arr[i].variant)
     return [w for _, w in keep]
 
 

@@ -41,7 +41,8 @@ class Problem(ctypes.Structure):
     _fields_ = [("X", Matrix), ("y", c_vp), ("x", c_vp), ("eta", c_dbl), ("lam", c_dbl),
                 ("b", c_i32), ("s", c_i32), ("seed", c_u64), ("outer_begin", c_u64),
                 ("n_outer", c_i64), ("ws", c_vp), ("ws_bytes", c_sz), ("groups", c_i32),
-                ("variant", c_i32), ("recur_prec", c_i32), ("loss", c_i32)]
+                ("variant", c_i32), ("recur_prec", c_i32), ("loss", c_i32),
+                ("snapshot_every", c_i64), ("x_history", c_vp), ("t_history", c_vp)]
 
 
 SLOTS = 7

@@ -11,6 +11,7 @@
 
 #include "internal.hpp"
 #include "misc.hpp"
+#include "recurrence.hpp"
 
 namespace casgd {
 
@@ -476,19 +477,30 @@ size_t casgd_batch_table_size(int32_t count) {
     return align256((size_t)count * sizeof(Dense)) + (size_t)kBatchMaxWG * sizeof(int2);
 }
 
-// Cost model of one problem's fit on g workgroups: H outer iterations of
-// (fixed part: recurrence stream of G_L on one CU + barriers) + (parallel part:
-// Gram flops + row traffic spread over g workgroups). Rates are per workgroup.
-static double batch_time(const Dense& P, int dtype, int g) {
+// Cost model of one problem's fit on g workgroups: H outer iterations of a
+// fixed part (the recurrence and the barriers) plus a parallel part (Gram
+// flops and row traffic spread over the group). Rates per workgroup, from
+// measurements on MI355X: the single-workgroup recurrence streams G_L at
+// about 6 GB/s (320 us at b = 64, s = 16), the chain + helper form takes
+// about 1.5 us per step plus two barriers.
+static double batch_time(const Dense& P, int dtype, int variant, int g) {
     const double gl = 4.0 * P.b * (double)P.b * P.s * (P.s - 1) / 2.0;
-    const double fixed = gl / 100e9 + 4e-6;
-    const double flop_rate = dtype == CASGD_F32 ? 0.3e12 : 2.0e12;
+    const double fixed = variant == 3 ? 1.5e-6 * P.s + 10e-6
+                                      : (variant == 2 ? gl / 6e9 + 6e-6 : gl / 6e9 + 3e-6);
+    const double flop_rate = dtype == CASGD_F32 ? 0.3e12 : 1.0e12;
     const double par = (double)P.s * (P.s - 1) * P.b * P.b * P.n / flop_rate +
                        3.0 * P.sb * (double)P.ldy * dtype_bytes(dtype) / 40e9;
     return (double)P.H * (fixed + par / g);
 }
 
-casgd_status casgd_fit_batch(const casgd_problem* probs, int32_t count, int64_t spin_limit,
+// Workgroups a variant needs at least: the recurrence group of variant 3
+// (which also claims the Gram units when nobody else is there), one
+// recurrence workgroup plus one Gram workgroup for variant 2, one otherwise.
+static int batch_minimum(const Dense& P, int variant) {
+    return variant == 3 ? 1 + rec_helpers(P.b, P.s) : (variant == 2 ? 2 : 1);
+}
+
+casgd_status casgd_fit_batch(casgd_problem* probs, int32_t count, int64_t spin_limit,
                              void* table, size_t table_bytes, void* stream) {
     if (!probs || count < 1) {
         set_error("need at least one problem");
@@ -499,7 +511,8 @@ casgd_status casgd_fit_batch(const casgd_problem* probs, int32_t count, int64_t 
     if ((rc = check_ws(table, table_bytes, need)) != CASGD_OK) return rc;
     const int dtype = probs[0].X.dtype;
     std::vector<Dense> D((size_t)count);
-    std::vector<int> groups((size_t)count), minimum((size_t)count);
+    std::vector<int> groups((size_t)count), minimum((size_t)count), variant((size_t)count);
+    std::vector<char> autov((size_t)count, 0);
     size_t lds = 0;
     hipStream_t st = (hipStream_t)stream;
     for (int i = 0; i < count; ++i) {
@@ -518,6 +531,9 @@ casgd_status casgd_fit_batch(const casgd_problem* probs, int32_t count, int64_t 
         o.recur_prec = q.recur_prec;
         o.fused_variant = q.variant;
         o.loss = q.loss;
+        o.snapshot_every = q.snapshot_every;
+        o.x_history = q.x_history;
+        o.t_history = q.t_history;
         rc = make_dense(&q.X, q.y, q.x, q.eta, q.lambda, q.b, q.s, q.seed, &o, q.ws, q.ws_bytes,
                         &D[i], &L, true);
         if (rc != CASGD_OK) {
@@ -527,32 +543,49 @@ casgd_status casgd_fit_batch(const casgd_problem* probs, int32_t count, int64_t 
         }
         FitPlan plan;
         if ((rc = plan_fit(D[i], dtype, &o, q.n_outer, &plan)) != CASGD_OK) return rc;
-        if (plan.variant == 3) {
-            // the batched launch runs the single-workgroup recurrence
-            if (q.variant == 3) {
-                set_error("problem %d: fused_variant 3 is not available in a batched launch", i);
-                return CASGD_EUNSUPPORTED;
-            }
-            plan.variant = 2;
-        }
         D[i].h0 = q.outer_begin;
         D[i].H = q.n_outer;
-        D[i].variant = plan.variant;
         D[i].recur64 = plan.recur64;
         D[i].tpr = recurrence_tpr(kNT, q.b);
+        variant[i] = plan.variant;
+        autov[i] = q.variant == 0 && plan.variant == 3;
         lds = std::max(lds, fit_lds(D[i], dtype, plan.recur64));
-        minimum[i] = plan.variant == 2 ? 2 : 1;
         groups[i] = q.groups;
-        if (q.groups > 0 && q.groups < minimum[i]) {
-            set_error("problem %d: variant 2 needs at least 2 workgroups", i);
-            return CASGD_EINVAL;
-        }
     }
     if (lds > 65536) {
         set_error("a problem of the batch needs more LDS than the fused kernel has");
         return CASGD_EUNSUPPORTED;
     }
     const int maxg = std::min(batch_max_grid(dtype, lds), kBatchMaxWG);
+    // Automatic variant 3 needs its whole recurrence group resident: when the
+    // groups do not fit, problems fall back to variant 2, those whose
+    // modelled gain from variant 3 is smallest first.
+    auto total_min = [&]() {
+        int t = 0;
+        for (int i = 0; i < count; ++i) t += groups[i] > 0 ? groups[i] : batch_minimum(D[i], variant[i]);
+        return t;
+    };
+    while (total_min() > maxg) {
+        int pick = -1;
+        double best = 0.0;
+        for (int i = 0; i < count; ++i) {
+            if (!autov[i] || variant[i] != 3 || groups[i] > 0) continue;
+            const int g3 = batch_minimum(D[i], 3);
+            const double gain = batch_time(D[i], dtype, 2, g3) - batch_time(D[i], dtype, 3, g3);
+            if (pick < 0 || gain < best) { pick = i; best = gain; }
+        }
+        if (pick < 0) break;
+        variant[pick] = 2;
+    }
+    for (int i = 0; i < count; ++i) {
+        D[i].variant = variant[i];
+        minimum[i] = batch_minimum(D[i], variant[i]);
+        if (groups[i] > 0 && groups[i] < minimum[i]) {
+            set_error("problem %d: variant %d needs at least %d workgroups", i, variant[i],
+                      minimum[i]);
+            return CASGD_EINVAL;
+        }
+    }
     int fixed = 0, need_min = 0;
     for (int i = 0; i < count; ++i) {
         if (groups[i] > 0) fixed += groups[i];
@@ -572,11 +605,11 @@ casgd_status casgd_fit_batch(const casgd_problem* probs, int32_t count, int64_t 
         double wt = -1.0;
         for (int i = 0; i < count; ++i) {
             if (groups[i] >= 0) continue;
-            const double t = batch_time(D[i], dtype, -groups[i]);
+            const double t = batch_time(D[i], dtype, variant[i], -groups[i]);
             if (t > wt) { wt = t; worst = i; }
         }
         if (worst < 0) break;
-        const double gain = wt - batch_time(D[worst], dtype, -groups[worst] + 1);
+        const double gain = wt - batch_time(D[worst], dtype, variant[worst], -groups[worst] + 1);
         if (gain <= 1e-3 * wt) break;
         --groups[worst];
         --spare;
@@ -592,6 +625,10 @@ casgd_status casgd_fit_batch(const casgd_problem* probs, int32_t count, int64_t 
         if ((rc = run_zero(D[i].tile_cnt, 2 * D[i].ntiles, st)) != CASGD_OK) return rc;
         if ((rc = run_zero(D[i].flags + FLAG_BAR_COUNT, FLAG_WORDS - FLAG_BAR_COUNT, st)) != CASGD_OK)
             return rc;
+        if (D[i].variant == 3 &&
+            (rc = run_zero(reinterpret_cast<unsigned*>(D[i].pub), (int64_t)D[i].sb * 8, st)) !=
+                CASGD_OK)
+            return rc;
     }
     char* tb = static_cast<char*>(table);
     Dense* tdev = reinterpret_cast<Dense*>(tb);
@@ -601,7 +638,12 @@ casgd_status casgd_fit_batch(const casgd_problem* probs, int32_t count, int64_t 
                              st));
     CASGD_HIP(hipStreamSynchronize(st));
     const unsigned long long spin = spin_limit > 0 ? (unsigned long long)spin_limit : (1ull << 24);
-    return run_fit_batch(tdev, mdev, grid, dtype, lds, spin, st);
+    if ((rc = run_fit_batch(tdev, mdev, grid, dtype, lds, spin, st)) != CASGD_OK) return rc;
+    for (int i = 0; i < count; ++i) {
+        probs[i].groups = D[i].gsize;
+        probs[i].variant = D[i].variant;
+    }
+    return CASGD_OK;
 }
 
 casgd_status casgd_sample_indices(uint64_t seed, uint64_t t0, int64_t count, int64_t m,

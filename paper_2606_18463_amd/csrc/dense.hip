@@ -81,9 +81,9 @@ __global__ __launch_bounds__(kNT) void k_fit_batch(const Dense* table, const int
     const Dense& P = table[__builtin_amdgcn_readfirstlane(me.x)];
     const int wg = __builtin_amdgcn_readfirstlane(me.y);
     if (P.recur64)
-        fit_body<DT, double, false>(P, wg, P.gsize, spin, lds);
+        fit_body<DT, double, true>(P, wg, P.gsize, spin, lds);
     else
-        fit_body<DT, float, false>(P, wg, P.gsize, spin, lds);
+        fit_body<DT, float, true>(P, wg, P.gsize, spin, lds);
 }
 
 // ------------------------------------------------------------------ host

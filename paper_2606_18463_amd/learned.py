@@ -27,7 +27,22 @@ import numpy as np
 
 import paper_2606_18463_amd as cg
 
-ETA_GRID = [2.0 ** k for k in range(-3, 9)]
+# Step-size grid relative to the mean squared row norm r2 of the (rescaled)
+# problem: eta = 2^k / r2 (column scales spread row norms over orders of
+# magnitude, so an absolute grid misses the useful range).
+ETA_K = range(-4, 13)
+
+
+def mean_row_norm2(X) -> float:
+    """mean_i ||a_i||^2 = sum_k (variance_k + mean_k^2) from the column
+    statistics kernel (no host pass over X)."""
+    st = cg.casgd_colstats(X).double()
+    return float((st[:, 1] + st[:, 0] ** 2).sum())
+
+
+def eta_grid(X):
+    r2 = mean_row_norm2(X)
+    return [2.0 ** k / r2 for k in ETA_K]
 
 
 @dataclass
@@ -95,8 +110,10 @@ def fit(X, y, n, eta, lam, b, s, seed, n_outer, snapshot_every=0):
     return x, hist
 
 
-def best_eta(X, y, Xt, yt, n, lam, b, s, seed, n_outer, grid=ETA_GRID):
-    """Step size of `grid` with the lowest held-out loss after n_outer iterations."""
+def best_eta(X, y, Xt, yt, n, lam, b, s, seed, n_outer, grid=None):
+    """Step size of `grid` (default eta_grid(X)) with the lowest held-out loss
+    after n_outer iterations."""
+    grid = eta_grid(X) if grid is None else grid
     best = None
     for eta in grid:
         x, _ = fit(X, y, n, eta, lam, b, s, seed, n_outer)

@@ -116,3 +116,30 @@ def test_full_size_uneven_batch_sampled_check(cg):
         err = np.linalg.norm(xg - xo) / max(np.linalg.norm(xo), 1e-30)
         print(f"\n[c5 scale] problem {i} m={p.m} n={p.n} rel_err={err:.3e}")
         assert err < 1e-4, i
+
+
+@pytest.mark.parametrize("fmt", ["f32", "bf16"])
+def test_batch_variant3_equals_solo(cg, fmt):
+    """The chain + helper recurrence (fused variant 3) inside each problem's
+    workgroup group: automatic form and explicit groups, bitwise equal to
+    the solo fused variant 3 fits (the result does not depend on how many
+    workgroups share the Gram and update work), with snapshots per problem."""
+    probs = [q for q in _problems(cg, 8, 13, fmt) if q["s"] >= 4]
+    xs = [torch.zeros(q["p"].n, device="cuda") for q in probs]
+    hists = [torch.zeros(q["H"], q["p"].n, device="cuda") for q in probs]
+    ths = [torch.zeros(q["H"] + 1, dtype=torch.int64, device="cuda") for q in probs]
+    batch = [dict(X=q["X"], y=q["y"], x=xs[i], eta=q["eta"], lam=q["lam"], b=q["b"], s=q["s"],
+                  seed=q["seed"], n_outer=q["H"], snapshot_every=1, x_history=hists[i],
+                  t_history=ths[i], groups=(0 if i % 2 else 20))
+             for i, q in enumerate(probs)]
+    for ws in cg.casgd_fit_batch(batch):
+        cg.casgd_check(ws)
+    for i, q in enumerate(probs):
+        solo = torch.zeros(q["p"].n, device="cuda")
+        o = cg.opts(exec_mode=1, fused_variant=3)
+        cg.casgd_fit(q["X"], q["y"], solo, q["eta"], q["lam"], q["b"], q["s"], q["seed"], 0,
+                     q["H"], opts=o)
+        assert torch.equal(solo, xs[i]), i
+        assert torch.equal(hists[i][-1], xs[i])
+        t = ths[i].cpu().numpy()
+        assert np.all(np.diff(t) >= 0) and t[-1] > t[0]
