@@ -175,22 +175,25 @@ def gram_shapes_bench(cg, dtypes, reps=10):
             sb = s * b
             G = torch.empty(sb, sb, device="cuda")
             ws = cg.workspace(cg.casgd_workspace_size(X, b, s))
-            for h in range(2):
-                cg.casgd_gram_margin(X, None, b, s, SEED, h, G=G, ws=ws, stream=stream)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for h in range(reps):
-                cg.casgd_gram_margin(X, None, b, s, SEED, h, G=G, ws=ws, stream=stream)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            us = e0.elapsed_time(e1) * 1e3 / reps
-            fl = gram_flops(b, s, n)
-            rows.append({"m": m, "n": n, "b": b, "s": s, "storage": dt,
-                         "us_per_call_with_gather": round(us, 3),
-                         "gram_flops": fl, "paper_flops": 2.0 * sb * sb * n})
-            log(f"[gram] m={m} n={n} b={b} s={s} {dt}: {us:.2f} us per call "
-                f"({fl / (us * 1e-6) / 1e12:.1f} TFLOP/s incl. gather)")
+            for tile in (64, 128):
+                o = cg.opts(gram_tile=tile)
+                for h in range(2):
+                    cg.casgd_gram_margin(X, None, b, s, SEED, h, G=G, ws=ws, stream=stream, opts=o)
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for h in range(reps):
+                    cg.casgd_gram_margin(X, None, b, s, SEED, h, G=G, ws=ws, stream=stream, opts=o)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                us = e0.elapsed_time(e1) * 1e3 / reps
+                fl = gram_flops(b, s, n)
+                rows.append({"m": m, "n": n, "b": b, "s": s, "storage": dt, "gram_tile": tile,
+                             "us_per_call_with_gather": round(us, 3),
+                             "gram_flops": fl, "paper_flops": 2.0 * sb * sb * n})
+                log(f"[gram] m={m} n={n} b={b} s={s} {dt} tile {tile}: {us:.2f} us per call "
+                    f"({fl / (us * 1e-6) / 1e12:.1f} TFLOP/s incl. gather)")
             del G, ws, X, keep
         del X32
         torch.cuda.empty_cache()

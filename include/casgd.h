@@ -172,6 +172,14 @@ typedef struct {
      * the FP16 recipe's accumulate-in-FP16 slots are not emulated). The
      * corrections run in FP32 (recur_prec 64 is rejected). */
     int32_t e2e;
+    /* Gram work units (0 = automatic): 64 = 64 x 64 (or 32 x 64) tiles whose
+     * four waves split K and read their operands directly; 128 = 128 x 128
+     * tiles with both row panels staged through LDS (more reuse per byte,
+     * fewer and larger units). Automatic: 128 when there are at least half
+     * as many such tiles as compute units (as many for FP32 storage; the
+     * group's workgroups in a batched launch). Results of the two agree to
+     * rounding. */
+    int32_t gram_tile;
 } casgd_opts;
 
 const char *casgd_status_string(casgd_status st);
@@ -295,6 +303,8 @@ typedef struct {
     int64_t snapshot_every;
     float *x_history;
     int64_t *t_history;
+    int32_t gram_tile;   /* as casgd_opts.gram_tile (0 = automatic for this problem's group) */
+    int32_t reserved;
 } casgd_problem;
 
 /* Bytes of the device table workspace of a batch of `count` problems. */
@@ -312,7 +322,9 @@ size_t casgd_batch_table_size(int32_t count);
  * `groups` and `variant` fields. The problem
  * table is uploaded to `table` (device, casgd_batch_table_size bytes) with a
  * synchronous copy before the launch. spin_limit as in casgd_opts (0 =
- * default). Results equal casgd_fit per problem for the same variant.
+ * default). Results equal casgd_fit per problem for the same variant and
+ * Gram unit kind (gram_tile); the automatic kind may differ between a
+ * problem's group and the whole device, and the two kinds agree to rounding.
  */
 casgd_status casgd_fit_batch(casgd_problem *probs, int32_t count, int64_t spin_limit,
                              void *table, size_t table_bytes, void *stream);
@@ -328,11 +340,14 @@ casgd_status casgd_sample_indices(uint64_t seed, uint64_t t0, int64_t count, int
  * Gram steps): r (device, FP32, s*b) = Y x and G (device, FP32, s*b x s*b,
  * row-major) with the strict block-lower entries G[t][u] = Y_t . Y_u,
  * block(u) < block(t), written; other entries are left untouched. x and r
- * may both be NULL to compute the Gram alone.
+ * may both be NULL to compute the Gram alone. opts (may be NULL): gram_tile
+ * selects the Gram unit kind as for a fit (automatic: 128 x 128 tiles when
+ * there are at least as many as compute units).
  */
 casgd_status casgd_gram_margin(const casgd_matrix *X, const float *x, int32_t b,
                                int32_t s, uint64_t seed, uint64_t outer_iter, float *G,
-                               float *r, void *ws, size_t ws_bytes, void *stream);
+                               float *r, const casgd_opts *opts, void *ws, size_t ws_bytes,
+                               void *stream);
 
 /*
  * The s residual corrections (Algorithm 1, inner loop, with decay) from

@@ -123,7 +123,7 @@ def _loss_code(loss) -> int:
 
 def opts(recur_prec: int = 0, exec_mode: int = 0, snapshot_every: int = 0, x_history=None,
          t_history=None, spin_limit: int = 0, fused_variant: int = 0, grid_blocks: int = 0,
-         phase_trace=None, rec_split: int = 0, loss=0, e2e: int = 0):
+         phase_trace=None, rec_split: int = 0, loss=0, e2e: int = 0, gram_tile: int = 0):
     """casgd_opts; phase_trace: device int64 tensor of 8 words per traced outer iteration;
     loss: "logistic", "linear", "poisson" or its code; e2e: 0, 1 (BF16), 2 (FP16)."""
     o = _lib.Opts(recur_prec=recur_prec, exec_mode=exec_mode, snapshot_every=snapshot_every,
@@ -131,7 +131,7 @@ def opts(recur_prec: int = 0, exec_mode: int = 0, snapshot_every: int = 0, x_his
                   fused_variant=fused_variant, grid_blocks=grid_blocks,
                   phase_trace=_ptr(phase_trace),
                   phase_trace_outer=0 if phase_trace is None else phase_trace.numel() // 8,
-                  rec_split=rec_split, loss=_loss_code(loss), e2e=e2e)
+                  rec_split=rec_split, loss=_loss_code(loss), e2e=e2e, gram_tile=gram_tile)
     o._keep = (x_history, t_history, phase_trace)
     return o
 
@@ -247,7 +247,8 @@ def casgd_fit_batch(problems, spin_limit: int = 0, stream=None):
                               loss=_loss_code(q.get("loss", 0)),
                               snapshot_every=q.get("snapshot_every", 0),
                               x_history=_ptr(q.get("x_history")),
-                              t_history=_ptr(q.get("t_history")))
+                              t_history=_ptr(q.get("t_history")),
+                              gram_tile=q.get("gram_tile", 0), reserved=0)
     tb = workspace(int(_L().casgd_batch_table_size(n)))
     _check(_L().casgd_fit_batch(arr, n, spin_limit, _ptr(tb), tb.numel(), _stream(stream)))
     for i, q in enumerate(problems):
@@ -264,7 +265,7 @@ def casgd_sample_indices(seed: int, t0: int, count: int, m: int, out=None, strea
 
 
 def casgd_gram_margin(X: MatrixRef, x, b: int, s: int, seed: int, outer_iter: int, G=None,
-                      r=None, ws=None, stream=None):
+                      r=None, ws=None, stream=None, opts=None):
     torch = _torch()
     sb = s * b
     G = G if G is not None else torch.zeros(sb, sb, dtype=torch.float32, device="cuda")
@@ -272,7 +273,7 @@ def casgd_gram_margin(X: MatrixRef, x, b: int, s: int, seed: int, outer_iter: in
         r = torch.zeros(sb, dtype=torch.float32, device="cuda")
     ws, nb = _ws(ws, casgd_workspace_size(X, b, s))
     _check(_L().casgd_gram_margin(X.ref(), _ptr(x), b, s, seed, outer_iter, _ptr(G), _ptr(r),
-                                  _ptr(ws), nb, _stream(stream)))
+                                  _opts_ref(opts), _ptr(ws), nb, _stream(stream)))
     return G, r
 
 

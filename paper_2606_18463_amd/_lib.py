@@ -34,7 +34,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("recur_prec", c_i32), ("exec_mode", c_i32), ("snapshot_every", c_i64),
                 ("x_history", c_vp), ("t_history", c_vp), ("spin_limit", c_i64),
                 ("fused_variant", c_i32), ("grid_blocks", c_i32), ("phase_trace", c_vp),
-                ("phase_trace_outer", c_i64), ("rec_split", c_i32), ("loss", c_i32), ("e2e", c_i32)]
+                ("phase_trace_outer", c_i64), ("rec_split", c_i32), ("loss", c_i32), ("e2e", c_i32),
+                ("gram_tile", c_i32)]
 
 
 class Problem(ctypes.Structure):
@@ -42,7 +43,8 @@ class Problem(ctypes.Structure):
                 ("b", c_i32), ("s", c_i32), ("seed", c_u64), ("outer_begin", c_u64),
                 ("n_outer", c_i64), ("ws", c_vp), ("ws_bytes", c_sz), ("groups", c_i32),
                 ("variant", c_i32), ("recur_prec", c_i32), ("loss", c_i32),
-                ("snapshot_every", c_i64), ("x_history", c_vp), ("t_history", c_vp)]
+                ("snapshot_every", c_i64), ("x_history", c_vp), ("t_history", c_vp),
+                ("gram_tile", c_i32), ("reserved", c_i32)]
 
 
 SLOTS = 7
@@ -88,8 +90,8 @@ SIGNATURES = {
     "casgd_fit_path": (c_i32, [PM, c_vp, c_vp, ctypes.POINTER(c_dbl), c_i32, c_dbl, c_i32, c_i32,
                                c_u64, c_u64, c_i64, PO, c_vp, c_sz, c_vp]),
     "casgd_sample_indices": (c_i32, [c_u64, c_u64, c_i64, c_i64, c_vp, c_vp]),
-    "casgd_gram_margin": (c_i32, [PM, c_vp, c_i32, c_i32, c_u64, c_u64, c_vp, c_vp, c_vp, c_sz,
-                                  c_vp]),
+    "casgd_gram_margin": (c_i32, [PM, c_vp, c_i32, c_i32, c_u64, c_u64, c_vp, c_vp, PO, c_vp,
+                                  c_sz, c_vp]),
     "casgd_recurrence_workspace_size": (c_sz, [c_i32, c_i32]),
     "casgd_recurrence": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_dbl, c_dbl, c_i32, c_i32, c_i32,
                                  c_vp, c_vp, c_vp, c_sz, c_vp]),

@@ -71,6 +71,17 @@ bool dense_layout(int64_t n, int dtype, int b, int s, DenseLayout* L) {
             if ((TI * kTile) / b < rlast / b) ++needed;
         }
     L->needed = needed;
+    {
+        const int T = tiles128_per_side(sb);
+        L->t128 = T * (T + 1) / 2;
+        int n128 = 0;
+        for (int TJ = 0; TJ < T; ++TJ)
+            for (int TI = 0; TI <= TJ; ++TI) {
+                const int rlast = std::min(TJ * kBig + kBig - 1, sb - 1);
+                if ((TI * kBig) / b < rlast / b) ++n128;
+            }
+        L->n128 = n128;
+    }
     L->bt = (b % kTile == 0) ? b / kTile : 0;
     L->gt = L->bt > 0 ? needed : L->ntiles;
     const int kstep = 4 * dtype_vec(dtype);
@@ -123,7 +134,7 @@ bool dense_layout(int64_t n, int dtype, int b, int s, DenseLayout* L) {
     off = align256(off + (size_t)sb * 4);
     L->off_pub = off;   // recurrence exchange: 2 * sb values of up to two words
     off = align256(off + (size_t)sb * 4 * sizeof(unsigned long long));
-    const size_t sbpad = (size_t)L->ts * kTile;   // rows padded to whole Gram tiles
+    const size_t sbpad = (size_t)(sb + 127) / 128 * 128;   // rows padded to whole 128-row tiles
     for (int k = 0; k < 3; ++k) {
         L->off_Y[k] = off;
         off = align256(off + sbpad * L->ldy * dtype_bytes(dtype));
@@ -147,6 +158,8 @@ void dense_bind(const DenseLayout& L, void* ws, Dense* P) {
     P->ksplit = L.ksplit;
     P->kchunk = L.kchunk;
     P->nslices = L.nslices;
+    P->t128 = L.t128;
+    P->g128 = 0;
     P->flags = reinterpret_cast<unsigned*>(w + L.off_flags);
     P->tile_cnt = reinterpret_cast<unsigned*>(w + L.off_tilecnt);
     P->G[0] = reinterpret_cast<float*>(w + L.off_G0);
@@ -618,6 +631,9 @@ casgd_status casgd_fit_batch(casgd_problem* probs, int32_t count, int64_t spin_l
     for (int i = 0; i < count; ++i) {
         const int g = std::abs(groups[i]);
         D[i].gsize = g;
+        const int nrec = variant[i] == 3 ? 1 + rec_helpers(D[i].b, D[i].s)
+                                         : (variant[i] == 2 ? 1 : 0);
+        D[i].g128 = choose_gram128(D[i], dtype, probs[i].gram_tile, std::max(1, g - nrec));
         for (int r = 0; r < g; ++r) wgmap.push_back(make_int2(i, r));
     }
     const int grid = (int)wgmap.size();
@@ -656,8 +672,8 @@ casgd_status casgd_sample_indices(uint64_t seed, uint64_t t0, int64_t count, int
 }
 
 casgd_status casgd_gram_margin(const casgd_matrix* X, const float* x, int32_t b, int32_t s,
-                               uint64_t seed, uint64_t outer_iter, float* G, float* r, void* ws,
-                               size_t ws_bytes, void* stream) {
+                               uint64_t seed, uint64_t outer_iter, float* G, float* r,
+                               const casgd_opts* opts, void* ws, size_t ws_bytes, void* stream) {
     if (!G || (!x) != (!r)) {
         set_error("G must not be NULL, and x and r must both be given or both be NULL");
         return CASGD_EINVAL;
@@ -668,6 +684,12 @@ casgd_status casgd_gram_margin(const casgd_matrix* X, const float* x, int32_t b,
                                  ws, ws_bytes, &P, &L, true);
     if (rc != CASGD_OK) return rc;
     P.ldg = P.sb;   // the caller's G is sb x sb
+    const int gram_tile = opts ? opts->gram_tile : 0;
+    if (gram_tile != 0 && gram_tile != 64 && gram_tile != 128) {
+        set_error("gram_tile must be 0, 64 or 128 (got %d)", gram_tile);
+        return CASGD_EINVAL;
+    }
+    P.g128 = choose_gram128(P, X->dtype, gram_tile, device_cus());
     hipStream_t st = (hipStream_t)stream;
     if ((rc = run_zero(P.tile_cnt, 2 * P.ntiles, st)) != CASGD_OK) return rc;
     if ((rc = run_gather(P, X->dtype, outer_iter, st)) != CASGD_OK) return rc;

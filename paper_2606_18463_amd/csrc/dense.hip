@@ -39,6 +39,13 @@ __global__ __launch_bounds__(kNT) void k_gram(Dense P, float* Gout, uint64_t h) 
     gram_phase<DT>(P, Gout, h, 0, gridDim.x, lds);
 }
 
+// One 128 x 128 LDS tile per workgroup.
+template <int DT>
+__global__ __launch_bounds__(kNT) void k_gram128(Dense P, float* Gout, uint64_t h) {
+    __shared__ __align__(16) unsigned char lds[kGram128Lds];
+    gram_tile128<DT>(P, Gout, h, blockIdx.x, lds);
+}
+
 template <int DT>
 __global__ __launch_bounds__(kNT) void k_update(Dense P, const float* c, uint64_t h, int do_update,
                                                 uint64_t hn, int do_margin, float* rp_out,
@@ -111,6 +118,11 @@ casgd_status launch_gather_reduce_t(const Dense& P, uint64_t h, int do_gather, c
 template <int DT>
 casgd_status launch_gram_t(const Dense& P, float* Gout, uint64_t h, hipStream_t st) {
     if (P.gt == 0 || P.s < 2) return CASGD_OK;
+    if (P.g128) {
+        hipLaunchKernelGGL(k_gram128<DT>, dim3(P.t128), dim3(kNT), 0, st, P, Gout, h);
+        CASGD_HIP(hipGetLastError());
+        return CASGD_OK;
+    }
     const int grid = (P.gna == 4 ? P.gt : 2 * P.gt) * P.ksplit;
     hipLaunchKernelGGL(k_gram<DT>, dim3(grid), dim3(kNT), 0, st, P, Gout, h);
     CASGD_HIP(hipGetLastError());
@@ -309,6 +321,18 @@ static int fit_max_grid_dt(const Dense& P, int dtype, int recur64) {
     }
 }
 
+bool choose_gram128(const Dense& P, int dtype, int gram_tile, int gram_workgroups) {
+    if (P.s < 2) return false;
+    if (gram_tile == 128) return true;
+    if (gram_tile == 64) return false;
+    DenseLayout L;
+    dense_layout(P.n, dtype, P.b, P.s, &L);
+    // measured on MI355X: with low-precision storage the LDS tiles win from
+    // about one tile per two Gram workgroups on; FP32 (four MFMAs per
+    // 16-byte operand) needs one per workgroup
+    return dtype == CASGD_F32 ? L.n128 >= gram_workgroups : 2 * L.n128 >= gram_workgroups;
+}
+
 casgd_status plan_fit(const Dense& P, int dtype, const casgd_opts* o, int64_t H, FitPlan* plan) {
     const int64_t sb = P.sb;
     int prec = o ? o->recur_prec : 0;
@@ -343,6 +367,12 @@ casgd_status plan_fit(const Dense& P, int dtype, const casgd_opts* o, int64_t H,
     }
     plan->variant = variant;
     plan->grid = 0;
+    const int gram_tile = o ? o->gram_tile : 0;
+    if (gram_tile != 0 && gram_tile != 64 && gram_tile != 128) {
+        set_error("gram_tile must be 0, 64 or 128 (got %d)", gram_tile);
+        return CASGD_EINVAL;
+    }
+    plan->gram128 = choose_gram128(P, dtype, gram_tile, device_cus());
     if (plan->exec_mode == 2) return CASGD_OK;
     const size_t lds = fit_lds_bytes(P.sb, P.s, plan->recur64 ? 8 : 4, slice_width_of(dtype));
     if (lds > 65536) {
@@ -354,7 +384,10 @@ casgd_status plan_fit(const Dense& P, int dtype, const casgd_opts* o, int64_t H,
         plan->exec_mode = 2;
         return CASGD_OK;
     }
-    const int units = P.s > 1 ? (P.gna == 4 ? P.gt : 2 * P.gt) * P.ksplit : 0;
+    DenseLayout L128;
+    dense_layout(P.n, dtype, P.b, P.s, &L128);
+    const int units = P.s > 1 ? (plan->gram128 ? L128.n128 : (P.gna == 4 ? P.gt : 2 * P.gt) * P.ksplit)
+                              : 0;
     // workgroups that run the recurrence while the others build the next Gram
     const int nrec = variant == 3 ? 1 + rec_helpers(P.b, P.s) : (variant == 2 ? 1 : 0);
     int want = std::max(P.nslices, units + nrec);
@@ -366,9 +399,11 @@ casgd_status plan_fit(const Dense& P, int dtype, const casgd_opts* o, int64_t H,
     return CASGD_OK;
 }
 
-casgd_status run_fit(const Dense& P, int dtype, uint64_t h0, int64_t H, const FitPlan& plan,
+casgd_status run_fit(const Dense& P0, int dtype, uint64_t h0, int64_t H, const FitPlan& plan,
                      hipStream_t st) {
     if (H <= 0) return CASGD_OK;
+    Dense P = P0;
+    P.g128 = plan.gram128;
     casgd_status rc;
     // Split-K counters must start at zero (they reset themselves after use,
     // but a launch that stopped early may leave them set).
@@ -386,6 +421,7 @@ casgd_status run_fit(const Dense& P, int dtype, uint64_t h0, int64_t H, const Fi
         Q.variant = plan.variant;
         Q.gsize = plan.grid;
         Q.recur64 = plan.recur64;
+        Q.g128 = plan.gram128;
         Q.tpr = recurrence_tpr(kNT, P.b);
         switch (dtype) {
             case DT_F32: return launch_fit_f32(Q, plan, st);

@@ -64,6 +64,8 @@ struct Dense {
     int tpr;                // threads per row of the recurrence
     int loss;               // LOSS_* (residual formula of the recurrence)
     int e2e;                // E2E_* end-to-end low-precision emulation
+    int g128;               // Gram units are 128 x 128 LDS tiles (gram_tile128)
+    int t128;               // lower-triangular 128-tiles enumerated
 };
 
 __device__ __forceinline__ int slot_of(uint64_t h) { return (int)(h % 3ull); }
@@ -182,7 +184,7 @@ __device__ __forceinline__ void gather_rows(const Dense& P, uint64_t h, int wave
     const int64_t nv = P.ldy / VEC;
     const uint64_t t0 = h * (uint64_t)P.sb;
     const V16 zero = {{0u, 0u, 0u, 0u}};
-    const int sbpad = (P.sb + kTile - 1) / kTile * kTile;
+    const int sbpad = (P.sb + 127) / 128 * 128;   // whole 128-row tiles
     for (int t = wave_id; t < sbpad; t += nwaves) {
         T* dst = Y + (int64_t)t * P.ldy;
         if (t >= P.sb) {  // padding rows of the last Gram tile: zeros
@@ -393,6 +395,146 @@ __device__ __forceinline__ void gram_unit(const Dense& P, float* Gout, uint64_t 
     }
 }
 
+// ------------------------------------------- Gram, 128 x 128 LDS tiles
+// A work unit of this kind is one 128 x 128 tile of the lower triangle of
+// G (on the 128 grid) over the whole K range, computed by the workgroup's
+// four waves as 2 x 2 quadrants of 64 x 64 (4 x 4 MFMA 16 x 16 tiles each).
+// Both row panels (128 rows x 128 bytes of K per chunk) are staged through
+// LDS, so every operand byte read from L2 feeds 128 rows of the tile (twice
+// the reuse of a 64-row unit whose waves read their operands directly). A
+// single LDS buffer with register prefetch: the global loads of chunk c+1
+// are issued before the MFMAs of chunk c and written to LDS after them;
+// barriers order LDS only, so the loads stay in flight across them. Row
+// pitch 144 bytes: the 16 rows a 16-lane group reads start on distinct
+// banks. Rows are zero-padded to a multiple of 128 and to whole chunks of K.
+constexpr int kBig = 128;                  // tile edge
+constexpr int kChunkB = 128;               // bytes of K per row per chunk
+constexpr int kRowB = kChunkB + 16;        // LDS row pitch
+constexpr size_t kGram128Lds = 2 * (size_t)kBig * kRowB;
+
+__host__ __device__ inline int tiles128_per_side(int sb) { return (sb + kBig - 1) / kBig; }
+
+// Lower-triangular 128-tile p; false when it holds no strict block-lower entry.
+__device__ __forceinline__ bool tile128_of(const Dense& P, int p, int& TJ, int& TI) {
+    tile_coords(p, TJ, TI);
+    const int rlast = min(TJ * kBig + kBig - 1, P.sb - 1);
+    return (TI * kBig) / P.b < rlast / P.b;
+}
+
+template <int DT>
+__device__ __forceinline__ void gram_tile128(const Dense& P, float* Gout, uint64_t h, int tile,
+                                             unsigned char* lds) {
+    using T = typename Store<DT>::T;
+    int TJ, TI;
+    if (!tile128_of(P, tile, TJ, TI)) return;   // the same for the whole workgroup
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wy = w >> 1, wx = w & 1;
+    const int slot = slot_of(h);
+    const unsigned char* Yb = static_cast<const unsigned char*>(pick3(P.Y, slot));
+    const int64_t ldb = P.ldy * (int64_t)sizeof(T);
+    const int nch = (int)((P.n * (int64_t)sizeof(T) + kChunkB - 1) / kChunkB);
+    unsigned char* As = lds;
+    unsigned char* Bs = lds + (size_t)kBig * kRowB;
+    // global -> LDS assignment: 1024 16-byte pieces per panel and chunk,
+    // piece v = tid + 256 i: row v / 8, segment v % 8
+    const unsigned char* ga[4];
+    const unsigned char* gb[4];
+    int lo[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int v = tid + 256 * i, row = v >> 3, seg = v & 7;
+        ga[i] = Yb + (int64_t)(TJ * kBig + row) * ldb + seg * 16;
+        gb[i] = Yb + (int64_t)(TI * kBig + row) * ldb + seg * 16;
+        lo[i] = row * kRowB + seg * 16;
+    }
+    // two register sets: the loads of chunk c+2 are issued before the MFMAs
+    // of chunk c (two chunks of MFMA work cover the L2 latency); every load
+    // is unconditional (past the end it re-reads the last chunk, unused)
+    u32x4 ra0[4], rb0[4], ra1[4], rb1[4];
+    auto gload = [&](u32x4 (&ra)[4], u32x4 (&rb)[4], int c) {
+        const int64_t off = (int64_t)(c < nch ? c : nch - 1) * kChunkB;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            ra[i] = *reinterpret_cast<const u32x4*>(ga[i] + off);
+            rb[i] = *reinterpret_cast<const u32x4*>(gb[i] + off);
+        }
+    };
+    v4f acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = v4f{0.f, 0.f, 0.f, 0.f};
+    const int ar = (wy * 64 + (lane & 15)) * kRowB, br = (wx * 64 + (lane & 15)) * kRowB;
+    auto stage = [&](const u32x4 (&ra)[4], const u32x4 (&rb)[4]) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            *reinterpret_cast<u32x4*>(As + lo[i]) = ra[i];
+            *reinterpret_cast<u32x4*>(Bs + lo[i]) = rb[i];
+        }
+    };
+    auto compute = [&]() {
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            const int so = ((lane >> 4) + 4 * half) * 16;
+            V16 av[4], bv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const u32x4 q = *reinterpret_cast<const u32x4*>(As + ar + a * 16 * kRowB + so);
+                av[a].w[0] = q[0]; av[a].w[1] = q[1]; av[a].w[2] = q[2]; av[a].w[3] = q[3];
+            }
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const u32x4 q = *reinterpret_cast<const u32x4*>(Bs + br + b * 16 * kRowB + so);
+                bv[b].w[0] = q[0]; bv[b].w[1] = q[1]; bv[b].w[2] = q[2]; bv[b].w[3] = q[3];
+            }
+#pragma unroll
+            for (int q = 0; q < mfma_per_vec<DT>(); ++q)
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) mfma_q<DT>(av[a], bv[b], q, acc[a][b]);
+        }
+    };
+    gload(ra0, rb0, 0);
+    gload(ra1, rb1, 1);
+#pragma unroll 1
+    for (int c = 0; c < nch; c += 2) {
+        stage(ra0, rb0);
+        lds_barrier();
+        gload(ra0, rb0, c + 2);
+        compute();
+        lds_barrier();
+        if (c + 1 < nch) {   // the same for the whole workgroup
+            stage(ra1, rb1);
+            lds_barrier();
+            gload(ra1, rb1, c + 3);
+            compute();
+            lds_barrier();
+        }
+    }
+    // store: lane l, register v hold row 4 (l / 16) + v, column l % 16 of a
+    // 16 x 16 tile; strict block-lower entries inside sb x sb only
+    const float* sI = pick3(P.sI, slot);
+    const int li = lane & 15, lg = lane >> 4;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int u = TI * kBig + wx * 64 + 16 * b + li;
+        const float sc = (P.scale && u < P.sb) ? sI[u] : 1.0f;
+        const int bu = u / P.b;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int t = TJ * kBig + wy * 64 + 16 * a + 4 * lg + v;
+                if (t < P.sb && u < P.sb && bu < t / P.b) {
+                    const float sr = P.scale ? sI[t] : 1.0f;
+                    Gout[(int64_t)t * P.ldg + u] = e2e_round(acc[a][b][v] * sr * sc, P.e2e);
+                }
+            }
+    }
+}
+
 // The Gram work of one outer iteration for the workgroups lo .. hi-1 of the
 // grid (physical indices). Work = units x K splits (units: whole tiles, or
 // half tiles when there are fewer tiles than compute units; see gna). With
@@ -403,9 +545,13 @@ template <int DT>
 __device__ __forceinline__ void gram_phase(const Dense& P, float* Gout, uint64_t h, int lo, int hi,
                                            unsigned char* lds) {
     const int w = blockIdx.x;
+    const int nw = hi - lo;
+    if (P.g128) {
+        for (int u = w - lo; u < P.t128; u += nw) gram_tile128<DT>(P, Gout, h, u, lds);
+        return;
+    }
     const int S = P.ksplit;
     const int U = P.gna == 4 ? P.gt : 2 * P.gt;
-    const int nw = hi - lo;
     if (nw >= S) {
         const int c = w % S;
         const int first = lo + ((c - lo % S) + S) % S;
@@ -432,7 +578,7 @@ template <int DT>
 __device__ __forceinline__ void gram_claim(const Dense& P, float* Gout, uint64_t h, unsigned* ctr,
                                            unsigned char* lds) {
     __shared__ unsigned s_unit;
-    const unsigned total = (unsigned)(P.gna == 4 ? P.gt : 2 * P.gt);
+    const unsigned total = (unsigned)(P.g128 ? P.t128 : (P.gna == 4 ? P.gt : 2 * P.gt));
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0)
@@ -440,7 +586,8 @@ __device__ __forceinline__ void gram_claim(const Dense& P, float* Gout, uint64_t
         __syncthreads();
         const unsigned u = s_unit;
         if (u >= total) break;
-        if (P.gna == 4) gram_unit<DT, 4>(P, Gout, h, (int)u, 0, lds);
+        if (P.g128) gram_tile128<DT>(P, Gout, h, (int)u, lds);
+        else if (P.gna == 4) gram_unit<DT, 4>(P, Gout, h, (int)u, 0, lds);
         else gram_unit<DT, 2>(P, Gout, h, (int)u, 0, lds);
     }
 }

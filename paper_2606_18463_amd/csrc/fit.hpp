@@ -58,7 +58,7 @@ __host__ __device__ inline size_t fit_lds_bytes(int sb, int s, int acc_bytes, in
     off += (size_t)sb * 4;                // c copy
     off += (size_t)kNW * kw * 4 + kw * 4; // red + xs
     // the Gram phase reuses the same memory (phases never overlap in a workgroup)
-    return s > 1 && off < kGramLds ? kGramLds : off;
+    return s > 1 && off < kGram128Lds ? kGram128Lds : off;
 }
 
 // One problem's whole fit on the workgroups wg = 0 .. nb-1 of its group (the
@@ -133,8 +133,8 @@ __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigne
             // With more Gram units than Gram workgroups (and no K split) the
             // units are claimed dynamically, and the recurrence workgroups join
             // once their chain is done; one round of units is dealt statically.
-            const int units = P.gna == 4 ? P.gt : 2 * P.gt;
-            const bool claim = P.ksplit == 1 && units > nb - nrec;
+            const int units = P.g128 ? P.t128 : (P.gna == 4 ? P.gt : 2 * P.gt);
+            const bool claim = (P.g128 || P.ksplit == 1) && units > nb - nrec;
             if (wg < nrec) {
                 rec_multi_rank<ACC>(P, pick2(P.G, cur), P.r, pick3(P.yI, slot_of(h)), P.c, spin, lds,
                                     wg);

@@ -26,7 +26,7 @@ int slice_width_of(int dtype);     // columns per update / margin slice
 
 // Workspace layout of one dense problem (byte offsets, 256-byte aligned).
 struct DenseLayout {
-    int sb, ts, ntiles, needed, gt, bt, gna, ksplit, nslices;
+    int sb, ts, ntiles, needed, gt, bt, gna, ksplit, nslices, t128, n128;
     int64_t kchunk, ldy, ldg;
     size_t off_flags, off_tilecnt, off_G0, off_G1, off_Gpart, off_rp0, off_rp1, off_c, off_r, off_pub,
         off_Y[3], off_yI[3], off_sI[3], total;
@@ -41,8 +41,14 @@ struct FitPlan {
     int variant;        // 1 redundant recurrence (one barrier/outer), 2 single recurrence group
     int grid;           // persistent grid size
     int recur64;        // FP64 recurrence
+    int gram128;        // Gram units are 128 x 128 LDS tiles
     unsigned long long spin;
 };
+
+// Gram unit kind: 128 x 128 LDS tiles when asked for (gram_tile 128), or
+// automatically when there are enough of them for the workgroups that build
+// the Gram (see choose_gram128).
+bool choose_gram128(const Dense& P, int dtype, int gram_tile, int gram_workgroups);
 
 casgd_status plan_fit(const Dense& P, int dtype, const casgd_opts* o, int64_t H, FitPlan* plan);
 casgd_status run_fit(const Dense& P, int dtype, uint64_t h0, int64_t H, const FitPlan& plan,

@@ -46,14 +46,14 @@ def test_batch_equals_solo_and_oracle(cg, fmt):
     probs = _problems(cg, 7, 5, fmt)
     xs = [torch.zeros(q["p"].n, device="cuda") for q in probs]
     batch = [dict(X=q["X"], y=q["y"], x=xs[i], eta=q["eta"], lam=q["lam"], b=q["b"], s=q["s"],
-                  seed=q["seed"], n_outer=q["H"], variant=2 if q["s"] > 1 else 1)
+                  seed=q["seed"], n_outer=q["H"], variant=2 if q["s"] > 1 else 1, gram_tile=64)
              for i, q in enumerate(probs)]
     wss = cg.casgd_fit_batch(batch)
     for ws in wss:
         cg.casgd_check(ws)
     for i, q in enumerate(probs):
         solo = torch.zeros(q["p"].n, device="cuda")
-        o = cg.opts(exec_mode=1, fused_variant=batch[i]["variant"])
+        o = cg.opts(exec_mode=1, fused_variant=batch[i]["variant"], gram_tile=64)
         cg.casgd_fit(q["X"], q["y"], solo, q["eta"], q["lam"], q["b"], q["s"], q["seed"], 0,
                      q["H"], opts=o)
         assert torch.equal(solo, xs[i]), i
@@ -67,13 +67,14 @@ def test_batch_explicit_groups(cg):
     probs = _problems(cg, 3, 9, "f32")
     xs = [torch.zeros(q["p"].n, device="cuda") for q in probs]
     batch = [dict(X=q["X"], y=q["y"], x=xs[i], eta=q["eta"], lam=q["lam"], b=q["b"], s=q["s"],
-                  seed=q["seed"], n_outer=q["H"], groups=3, variant=2 if q["s"] > 1 else 1)
+                  seed=q["seed"], n_outer=q["H"], groups=3, variant=2 if q["s"] > 1 else 1,
+                  gram_tile=64)
              for i, q in enumerate(probs)]
     for ws in cg.casgd_fit_batch(batch):
         cg.casgd_check(ws)
     for i, q in enumerate(probs):
         solo = torch.zeros(q["p"].n, device="cuda")
-        o = cg.opts(exec_mode=1, fused_variant=batch[i]["variant"])
+        o = cg.opts(exec_mode=1, fused_variant=batch[i]["variant"], gram_tile=64)
         cg.casgd_fit(q["X"], q["y"], solo, q["eta"], q["lam"], q["b"], q["s"], q["seed"], 0,
                      q["H"], opts=o)
         assert torch.equal(solo, xs[i]), i
@@ -119,7 +120,8 @@ def test_full_size_uneven_batch_sampled_check(cg):
 
 
 @pytest.mark.parametrize("fmt", ["f32", "bf16"])
-def test_batch_variant3_equals_solo(cg, fmt):
+@pytest.mark.parametrize("gram_tile", [64, 128])
+def test_batch_variant3_equals_solo(cg, fmt, gram_tile):
     """The chain + helper recurrence (fused variant 3) inside each problem's
     workgroup group: automatic form and explicit groups, bitwise equal to
     the solo fused variant 3 fits (the result does not depend on how many
@@ -130,13 +132,13 @@ def test_batch_variant3_equals_solo(cg, fmt):
     ths = [torch.zeros(q["H"] + 1, dtype=torch.int64, device="cuda") for q in probs]
     batch = [dict(X=q["X"], y=q["y"], x=xs[i], eta=q["eta"], lam=q["lam"], b=q["b"], s=q["s"],
                   seed=q["seed"], n_outer=q["H"], snapshot_every=1, x_history=hists[i],
-                  t_history=ths[i], groups=(0 if i % 2 else 20))
+                  t_history=ths[i], groups=(0 if i % 2 else 20), gram_tile=gram_tile)
              for i, q in enumerate(probs)]
     for ws in cg.casgd_fit_batch(batch):
         cg.casgd_check(ws)
     for i, q in enumerate(probs):
         solo = torch.zeros(q["p"].n, device="cuda")
-        o = cg.opts(exec_mode=1, fused_variant=3)
+        o = cg.opts(exec_mode=1, fused_variant=3, gram_tile=gram_tile)
         cg.casgd_fit(q["X"], q["y"], solo, q["eta"], q["lam"], q["b"], q["s"], q["seed"], 0,
                      q["H"], opts=o)
         assert torch.equal(solo, xs[i]), i

@@ -103,7 +103,8 @@ GRAM_CASES = [
 
 @pytest.mark.parametrize("fmt", ["f32", "bf16", "f16", "fp8"])
 @pytest.mark.parametrize("case", GRAM_CASES)
-def test_gram_margin_vs_oracle(cg, fmt, case):
+@pytest.mark.parametrize("gram_tile", [64, 128])
+def test_gram_margin_vs_oracle(cg, fmt, case, gram_tile):
     m, n, ld, b, s = case
     p = dense_logreg(m, n, 9, var=1.0 / n, noise_var=0.1, dtype=np.float32)
     X32 = p.X
@@ -116,7 +117,8 @@ def test_gram_margin_vs_oracle(cg, fmt, case):
     x = np.random.default_rng(5).standard_normal(n).astype(np.float32)
     sb = s * b
     for h in (0, 3):
-        G, r = cg.casgd_gram_margin(X, _to_dev(x), b, s, 42, h)
+        G, r = cg.casgd_gram_margin(X, _to_dev(x), b, s, 42, h,
+                                    opts=cg.opts(gram_tile=gram_tile))
         G = G.cpu().numpy().astype(np.float64)
         r = r.cpu().numpy().astype(np.float64)
         parts = R.outer_parts(exact, p.y, x.astype(np.float64), 0.5, 0.0, b, s, 42, h)

@@ -137,7 +137,8 @@ def local_check(cg, X, exact_rows, y, n, b, s, eta, lam, seed, H, loss="logistic
 
 
 FORMS = [dict(exec_mode=1, fused_variant=3), dict(exec_mode=1, fused_variant=2),
-         dict(exec_mode=1, fused_variant=1), dict(exec_mode=2)]
+         dict(exec_mode=1, fused_variant=1), dict(exec_mode=2),
+         dict(exec_mode=1, fused_variant=3, gram_tile=128), dict(exec_mode=2, gram_tile=128)]
 
 
 @pytest.mark.parametrize("b,s", [(16, 8), (32, 16), (64, 4), (64, 16), (64, 32), (128, 8)])
@@ -155,12 +156,14 @@ def test_fit_forms_each_outer_iteration(cg, data, b, s, form):
 
 @pytest.mark.parametrize("fmt", ["bf16", "f16", "fp8"])
 @pytest.mark.parametrize("b,s", [(32, 8), (64, 16), (128, 32)])
-def test_fit_low_precision_each_outer_iteration(cg, data, fmt, b, s):
+@pytest.mark.parametrize("gram_tile", [64, 128])
+def test_fit_low_precision_each_outer_iteration(cg, data, fmt, b, s, gram_tile):
     p = data["logistic"]
     X, keep = _stored(cg, p.X, fmt)
     _, _, exact = R.quantize(p.X, fmt)
     local_check(cg, X, lambda idx: exact[idx], p.y, 520, b, s, 0.5, 1e-4, 5, 4,
-                scaled=fmt == "fp8", what=f"{fmt} b={b} s={s}")
+                scaled=fmt == "fp8", what=f"{fmt} b={b} s={s} tile {gram_tile}",
+                gram_tile=gram_tile)
 
 
 @pytest.mark.parametrize("loss", ["linear", "poisson"])
