@@ -569,11 +569,11 @@ def c5_bench(cg, n_train: int, n_eval: int, epochs: float = 4.0):
         vf, _ = cg.casgd_quantize(dp.X32, cg.F32)         # FP32 storage, rows padded
         Xf = cg.dense_matrix(vf, None, n=dp.n)
         Xb = Lm.stored(dp)                                 # BF16 storage
-        q, eta_l = Lm.predict(model, Xb)
+        Xl, Xtl, q, eta_l = Lm.apply(model, dp)
         per_epoch = dp.m // b
         every = max(1, per_epoch // (16 * s))             # outer iterations per snapshot
         nsnap = max(4, int(epochs * per_epoch) // (every * s))
-        evals.append(dict(dp=dp, Xf=Xf, Xb=Xb, Xl=Lm.stored(dp, q), Xtl=Lm.stored_test(dp, q),
+        evals.append(dict(dp=dp, Xf=Xf, Xb=Xb, Xl=Xl, Xtl=Xtl,
                           eta_p=g["eta"], eta_l=eta_l, L_star=g["L_star"], every=every,
                           nsnap=nsnap, window=max(2, round(per_epoch / (every * s) / 2))))
         del p

@@ -11,8 +11,10 @@ Training targets come from runs of the plain method:
   * log d_k = -log H_kk (centred per problem), H_kk the diagonal of the
     Hessian of the regularised logistic loss at the plain method's solution
     (a Jacobi preconditioner);
-  * log eta = log of the best step size of a short sweep on the rescaled
-    problem.
+  * log (eta r2) = log of the best step size of a short sweep on the rescaled
+    problem times its mean squared row norm r2: a dimensionless step, so the
+    prediction does not have to learn the problem's scale (the absolute step
+    is the prediction divided by r2 of the rescaled problem).
 
 Everything numeric runs in libcasgd's kernels (column statistics, Hessian
 diagonal, MLP forward/backward/Adam, quantisation, fits, losses); this module
@@ -124,7 +126,7 @@ def best_eta(X, y, Xt, yt, n, lam, b, s, seed, n_outer, grid=None):
 
 
 def targets(dp: DeviceProblem, lam: float, b: int, s: int, seed: int, epochs: float = 2.0):
-    """(t_d per column, log eta for the rescaled problem, plain best eta)."""
+    """(t_d per column, log (eta r2) for the rescaled problem, plain best eta)."""
     X = stored(dp)
     n_outer = max(2, int(epochs * dp.m / (b * s)))
     short = max(2, n_outer // 4)
@@ -132,8 +134,11 @@ def targets(dp: DeviceProblem, lam: float, b: int, s: int, seed: int, epochs: fl
     x, _ = fit(X, dp.y, dp.n, eta0, lam, b, s, seed, n_outer)
     h = cg.casgd_hess_diag(X, x, lam)
     t_d, q = cg.casgd_jacobi_target(h)
-    eta1 = best_eta(stored(dp, q), dp.y, stored_test(dp, q), dp.yt, dp.n, lam, b, s, seed, short)
-    return t_d, math.log(eta1), eta0
+    Xq = stored(dp, q)
+    r2 = mean_row_norm2(Xq)
+    eta1 = best_eta(Xq, dp.y, stored_test(dp, q), dp.yt, dp.n, lam, b, s, seed, short,
+                    grid=[2.0 ** k / r2 for k in ETA_K])
+    return t_d, math.log(eta1 * r2), eta0
 
 
 def init_params(seed: int = 0):
@@ -178,12 +183,21 @@ def train(stats_list, t_d_list, t_eta_list, steps: int = 2000, lr: float = 3e-3,
 
 
 def predict(model: Model, X):
-    """(column scale q = sqrt(d), eta) for a problem from its column statistics."""
+    """(column scale q = sqrt(d), dimensionless step eta r2) for a problem from
+    its column statistics."""
     st = cg.casgd_colstats(X)
     feats = cg.casgd_mlp_features(st, model.norm)
     out, _ = cg.casgd_mlp_forward(model.params, feats, want_pre=False)
     q, eta = cg.casgd_mlp_apply(out)
     return q, float(eta)
+
+
+def apply(model: Model, dp: DeviceProblem):
+    """The preconditioned problem: (X~ = X diag(q) in the storage dtype, the
+    held-out rows scaled alike, q, absolute step size)."""
+    q, eta_rel = predict(model, stored(dp))
+    Xq = stored(dp, q)
+    return Xq, stored_test(dp, q), q, eta_rel / mean_row_norm2(Xq)
 
 
 def loss_curve(X, y, Xt, yt, n, eta, lam, b, s, seed, n_outer, every):

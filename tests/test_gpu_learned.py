@@ -43,7 +43,7 @@ def test_learned_preconditioner_generalises(L):
     corr, wins = [], 0
     for dp in test_p:
         X = L.stored(dp)
-        q, eta = L.predict(model, X)
+        Xq, _, q, eta = L.apply(model, dp)
         # predicted scale against the Jacobi target of the unseen problem
         t_d, _, eta0 = L.targets(dp, LAM, B, S, SEED, epochs=1.0)
         pred = 2.0 * torch.log(q)
@@ -51,7 +51,7 @@ def test_learned_preconditioner_generalises(L):
         n_outer = max(2, int(dp.m / (B * S)))
         x_plain, _ = L.fit(X, dp.y, dp.n, eta0, LAM, B, S, SEED, n_outer)
         lp = float(L.cg.casgd_logloss(dp.Xt, dp.yt, x_plain))
-        xt, _ = L.fit(L.stored(dp, q), dp.y, dp.n, eta, LAM, B, S, SEED, n_outer)
+        xt, _ = L.fit(Xq, dp.y, dp.n, eta, LAM, B, S, SEED, n_outer)
         ll = float(L.cg.casgd_logloss(dp.Xt, dp.yt, L.unscale(xt, q)))
         print("problem", dp.m, dp.n, "plain", lp, "learned", ll, "eta", eta0, eta)
         wins += ll < lp
