@@ -259,7 +259,11 @@ casgd_status casgd_path_workspace_size(const casgd_matrix *X, int32_t b, int32_t
 /* Prepare a workspace for a CSR X: column frequencies, head/tail split,
  * cleared buckets. Synchronous. Required once per (X, b, s, workspace) before
  * casgd_fit / casgd_step / casgd_fit_path on that CSR X; `lanes` is the largest
- * lane count that will be used. Its cost is not part of any iteration. */
+ * lane count that will be used. Its cost is not part of any iteration. The
+ * decisions (X's pointers and shape, b, s, lanes, the head split) are stored
+ * in the workspace itself; the library keeps no host state. A CSR fit reads
+ * that record back with a small synchronous device-to-host copy before it
+ * enqueues its launch. */
 casgd_status casgd_sparse_prepare(const casgd_matrix *X, int32_t b, int32_t s, int32_t lanes,
                                   void *ws, size_t ws_bytes, void *stream);
 

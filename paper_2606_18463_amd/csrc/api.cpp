@@ -15,15 +15,15 @@
 
 namespace casgd {
 
-static thread_local std::string t_err;
+// Per-thread message of the last failing call: a plain buffer, so that no
+// destructor runs at thread or process exit.
+static thread_local char t_err[512];
 
 void set_error(const char* fmt, ...) {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vsnprintf(t_err, sizeof t_err, fmt, ap);
     va_end(ap);
-    t_err = buf;
 }
 
 casgd_status hip_fail(hipError_t e, const char* what) {
@@ -375,7 +375,7 @@ const char* casgd_status_string(casgd_status st) {
     }
 }
 
-const char* casgd_last_error(void) { return t_err.c_str(); }
+const char* casgd_last_error(void) { return t_err; }
 
 int32_t casgd_version(void) { return 100; }
 
@@ -569,7 +569,9 @@ casgd_status casgd_fit_batch(casgd_problem* probs, int32_t count, int64_t spin_l
         set_error("a problem of the batch needs more LDS than the fused kernel has");
         return CASGD_EUNSUPPORTED;
     }
-    const int maxg = std::min(batch_max_grid(dtype, lds), kBatchMaxWG);
+    bool generic = false;   // some problem has another loss or end-to-end rounding
+    for (int i = 0; i < count; ++i) generic = generic || D[i].loss != 0 || D[i].e2e != 0;
+    const int maxg = std::min(batch_max_grid(dtype, lds, generic), kBatchMaxWG);
     // Automatic variant 3 needs its whole recurrence group resident: when the
     // groups do not fit, problems fall back to variant 2, those whose
     // modelled gain from variant 3 is smallest first.
@@ -654,7 +656,8 @@ casgd_status casgd_fit_batch(casgd_problem* probs, int32_t count, int64_t spin_l
                              st));
     CASGD_HIP(hipStreamSynchronize(st));
     const unsigned long long spin = spin_limit > 0 ? (unsigned long long)spin_limit : (1ull << 24);
-    if ((rc = run_fit_batch(tdev, mdev, grid, dtype, lds, spin, st)) != CASGD_OK) return rc;
+    if ((rc = run_fit_batch(tdev, mdev, grid, dtype, lds, spin, generic, st)) != CASGD_OK)
+        return rc;
     for (int i = 0; i < count; ++i) {
         probs[i].groups = D[i].gsize;
         probs[i].variant = D[i].variant;

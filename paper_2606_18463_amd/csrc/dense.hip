@@ -77,22 +77,6 @@ __global__ __launch_bounds__(kNT) void k_recurrence(Dense P, const float* G, con
     recurrence<ACC, kNT>(P, G, rp, h, r_in, y_in, c, delta_out, dl, pw, tpr);
 }
 
-// Many problems in one cooperative launch: workgroup w runs problem
-// wgmap[w].x as member wgmap[w].y of that problem's group (table[p].gsize
-// workgroups, contiguous). Each problem keeps its own workspace and barrier.
-template <int DT>
-__global__ __launch_bounds__(kNT) void k_fit_batch(const Dense* table, const int2* wgmap,
-                                                   unsigned long long spin) {
-    extern __shared__ __align__(16) unsigned char lds[];
-    const int2 me = wgmap[blockIdx.x];
-    const Dense& P = table[__builtin_amdgcn_readfirstlane(me.x)];
-    const int wg = __builtin_amdgcn_readfirstlane(me.y);
-    if (P.recur64)
-        fit_body<DT, double, true>(P, wg, P.gsize, spin, lds);
-    else
-        fit_body<DT, float, true>(P, wg, P.gsize, spin, lds);
-}
-
 // ------------------------------------------------------------------ host
 
 namespace {
@@ -154,28 +138,25 @@ size_t rec_lds(const Dense& P) {
 
 }  // namespace
 
-casgd_status run_fit_batch(const Dense* table_dev, const int2* wgmap_dev, int grid, int dtype,
-                           size_t lds, unsigned long long spin, hipStream_t st) {
-    const void* kern = nullptr;
+static const void* batch_kernel(int dtype, bool generic) {
     switch (dtype) {
-        case DT_F32: kern = reinterpret_cast<const void*>(k_fit_batch<DT_F32>); break;
-        case DT_BF16: kern = reinterpret_cast<const void*>(k_fit_batch<DT_BF16>); break;
-        case DT_F16: kern = reinterpret_cast<const void*>(k_fit_batch<DT_F16>); break;
-        default: kern = reinterpret_cast<const void*>(k_fit_batch<DT_FP8>); break;
+        case DT_F32: return batch_kernel_f32(generic);
+        case DT_BF16: return batch_kernel_bf16(generic);
+        case DT_F16: return batch_kernel_f16(generic);
+        default: return batch_kernel_fp8(generic);
     }
+}
+
+casgd_status run_fit_batch(const Dense* table_dev, const int2* wgmap_dev, int grid, int dtype,
+                           size_t lds, unsigned long long spin, bool generic, hipStream_t st) {
+    const void* kern = batch_kernel(dtype, generic);
     void* args[] = {const_cast<Dense**>(&table_dev), const_cast<int2**>(&wgmap_dev), &spin};
     CASGD_HIP(hipLaunchCooperativeKernel(kern, dim3(grid), dim3(kNT), args, (unsigned)lds, st));
     return CASGD_OK;
 }
 
-int batch_max_grid(int dtype, size_t lds) {
-    const void* kern = nullptr;
-    switch (dtype) {
-        case DT_F32: kern = reinterpret_cast<const void*>(k_fit_batch<DT_F32>); break;
-        case DT_BF16: kern = reinterpret_cast<const void*>(k_fit_batch<DT_BF16>); break;
-        case DT_F16: kern = reinterpret_cast<const void*>(k_fit_batch<DT_F16>); break;
-        default: kern = reinterpret_cast<const void*>(k_fit_batch<DT_FP8>); break;
-    }
+int batch_max_grid(int dtype, size_t lds, bool generic) {
+    const void* kern = batch_kernel(dtype, generic);
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kNT, lds) != hipSuccess) return 0;
     return per_cu * device_cus();

@@ -68,6 +68,14 @@ struct Dense {
     int t128;               // lower-triangular 128-tiles enumerated
 };
 
+// The residual formula and the end-to-end rounding mode of a problem. GEN =
+// false compiles the default (logistic, no rounding) as constants: the fused
+// kernels for that case then carry no run-time branch on them in the chain.
+template <bool GEN>
+__device__ __forceinline__ int loss_mode(const Dense& P) { return GEN ? P.loss : LOSS_LOGISTIC; }
+template <bool GEN>
+__device__ __forceinline__ int e2e_mode(const Dense& P) { return GEN ? P.e2e : E2E_OFF; }
+
 __device__ __forceinline__ int slot_of(uint64_t h) { return (int)(h % 3ull); }
 inline int slot_of_host(uint64_t h) { return (int)(h % 3ull); }
 
@@ -233,7 +241,7 @@ constexpr size_t kGramLds = 4 * 4 * 64 * 16 + 16;
 // than one split, the last workgroup to finish a unit adds the splits'
 // partials in split order. Rows are zero-padded to ldy and to a multiple of
 // kTile, so no load is guarded.
-template <int DT, int NA>
+template <int DT, int NA, bool GEN = true>
 __device__ __forceinline__ void gram_unit(const Dense& P, float* Gout, uint64_t h, int unit,
                                           int split, unsigned char* lds) {
     using T = typename Store<DT>::T;
@@ -389,7 +397,7 @@ __device__ __forceinline__ void gram_unit(const Dense& P, float* Gout, uint64_t 
             const int t = row0 + 16 * a + 4 * lg + v;
             if (t < P.sb && u < P.sb && bu < t / P.b) {
                 const float sr = P.scale ? sI[t] : 1.0f;
-                Gout[(int64_t)t * P.ldg + u] = e2e_round(part[a][v] * sr * sc, P.e2e);
+                Gout[(int64_t)t * P.ldg + u] = e2e_round(part[a][v] * sr * sc, e2e_mode<GEN>(P));
             }
         }
     }
@@ -421,7 +429,7 @@ __device__ __forceinline__ bool tile128_of(const Dense& P, int p, int& TJ, int& 
     return (TI * kBig) / P.b < rlast / P.b;
 }
 
-template <int DT>
+template <int DT, bool GEN = true>
 __device__ __forceinline__ void gram_tile128(const Dense& P, float* Gout, uint64_t h, int tile,
                                              unsigned char* lds) {
     using T = typename Store<DT>::T;
@@ -529,7 +537,8 @@ __device__ __forceinline__ void gram_tile128(const Dense& P, float* Gout, uint64
                 const int t = TJ * kBig + wy * 64 + 16 * a + 4 * lg + v;
                 if (t < P.sb && u < P.sb && bu < t / P.b) {
                     const float sr = P.scale ? sI[t] : 1.0f;
-                    Gout[(int64_t)t * P.ldg + u] = e2e_round(acc[a][b][v] * sr * sc, P.e2e);
+                    Gout[(int64_t)t * P.ldg + u] =
+                        e2e_round(acc[a][b][v] * sr * sc, e2e_mode<GEN>(P));
                 }
             }
     }
@@ -541,13 +550,13 @@ __device__ __forceinline__ void gram_tile128(const Dense& P, float* Gout, uint64
 // at least ksplit workers, worker w takes only split w % ksplit: workgroups
 // are dispatched to the eight XCDs round-robin and ksplit divides 8, so each
 // XCD reads one K range of the gathered rows. `lds` holds kGramLds bytes.
-template <int DT>
+template <int DT, bool GEN = true>
 __device__ __forceinline__ void gram_phase(const Dense& P, float* Gout, uint64_t h, int lo, int hi,
                                            unsigned char* lds) {
     const int w = blockIdx.x;
     const int nw = hi - lo;
     if (P.g128) {
-        for (int u = w - lo; u < P.t128; u += nw) gram_tile128<DT>(P, Gout, h, u, lds);
+        for (int u = w - lo; u < P.t128; u += nw) gram_tile128<DT, GEN>(P, Gout, h, u, lds);
         return;
     }
     const int S = P.ksplit;
@@ -557,13 +566,13 @@ __device__ __forceinline__ void gram_phase(const Dense& P, float* Gout, uint64_t
         const int first = lo + ((c - lo % S) + S) % S;
         const int members = (hi - first + S - 1) / S;
         for (int u = (w - first) / S; u < U; u += members) {
-            if (P.gna == 4) gram_unit<DT, 4>(P, Gout, h, u, c, lds);
-            else gram_unit<DT, 2>(P, Gout, h, u, c, lds);
+            if (P.gna == 4) gram_unit<DT, 4, GEN>(P, Gout, h, u, c, lds);
+            else gram_unit<DT, 2, GEN>(P, Gout, h, u, c, lds);
         }
     } else {
         for (int g = w - lo; g < U * S; g += nw) {
-            if (P.gna == 4) gram_unit<DT, 4>(P, Gout, h, g / S, g % S, lds);
-            else gram_unit<DT, 2>(P, Gout, h, g / S, g % S, lds);
+            if (P.gna == 4) gram_unit<DT, 4, GEN>(P, Gout, h, g / S, g % S, lds);
+            else gram_unit<DT, 2, GEN>(P, Gout, h, g / S, g % S, lds);
         }
     }
 }
@@ -574,7 +583,7 @@ __device__ __forceinline__ void gram_phase(const Dense& P, float* Gout, uint64_t
 // workgroups, once their chain is done) take what remains. Each unit is
 // computed whole by its workgroup: the result does not depend on who
 // computed what. `lds` holds kGramLds bytes.
-template <int DT>
+template <int DT, bool GEN = true>
 __device__ __forceinline__ void gram_claim(const Dense& P, float* Gout, uint64_t h, unsigned* ctr,
                                            unsigned char* lds) {
     __shared__ unsigned s_unit;
@@ -586,9 +595,9 @@ __device__ __forceinline__ void gram_claim(const Dense& P, float* Gout, uint64_t
         __syncthreads();
         const unsigned u = s_unit;
         if (u >= total) break;
-        if (P.g128) gram_tile128<DT>(P, Gout, h, (int)u, lds);
-        else if (P.gna == 4) gram_unit<DT, 4>(P, Gout, h, (int)u, 0, lds);
-        else gram_unit<DT, 2>(P, Gout, h, (int)u, 0, lds);
+        if (P.g128) gram_tile128<DT, GEN>(P, Gout, h, (int)u, lds);
+        else if (P.gna == 4) gram_unit<DT, 4, GEN>(P, Gout, h, (int)u, 0, lds);
+        else gram_unit<DT, 2, GEN>(P, Gout, h, (int)u, 0, lds);
     }
 }
 
@@ -600,7 +609,7 @@ __device__ __forceinline__ void gram_claim(const Dense& P, float* Gout, uint64_t
 // A row segment is read by kLPR lanes with 16-byte loads from the gathered
 // rows; NW waves share the rows and every lane keeps U rows in flight.
 // Uses LDS `red` (NW * width floats) and `xs` (width floats).
-template <int DT, int NW>
+template <int DT, int NW, bool GEN = true>
 __device__ __forceinline__ void update_margin_slice(const Dense& P, int slice, const float* c, uint64_t h,
                                     bool do_update, uint64_t hn, bool do_margin, float* rp_out,
                                     float* red, float* xs, int64_t snap_row) {
@@ -661,7 +670,8 @@ __device__ __forceinline__ void update_margin_slice(const Dense& P, int slice, c
                 float g = 0.f;
 #pragma unroll
                 for (int ww = 0; ww < NW; ++ww) g += red[ww * KW + q];
-                xn = e2e_round(P.beta_s * P.x[k] + P.alpha * e2e_round(g, P.e2e), P.e2e);
+                const int e2e = e2e_mode<GEN>(P);
+                xn = e2e_round(P.beta_s * P.x[k] + P.alpha * e2e_round(g, e2e), e2e);
                 P.x[k] = xn;
                 if (!isfinite(xn)) raise_flag(P.flags, FLAG_NONFINITE);
                 if (snap_row >= 0) P.x_hist[snap_row * P.n + k] = xn;
@@ -718,7 +728,7 @@ __device__ __forceinline__ void update_margin_slice(const Dense& P, int slice, c
 // 16-byte loads before consuming them.
 constexpr int kRB = 16;
 
-template <typename ACC, int NT>
+template <typename ACC, int NT, bool GEN = true>
 __device__ __forceinline__ void recurrence(const Dense& P, const float* G, const float* rp,
                                            uint64_t h, const float* r_in, const float* y_in,
                                            float* c, float* delta_out, ACC* dl, ACC* pw, int TPR) {
@@ -797,14 +807,15 @@ __device__ __forceinline__ void recurrence(const Dense& P, const float* G, const
                     r = (ACC)r_in[t];
                     yv = (ACC)y_in[t];
                 } else {
-                    r = e2e_round(rr * (ACC)pick3(P.sI, slot)[t], P.e2e);
+                    r = e2e_round(rr * (ACC)pick3(P.sI, slot)[t], e2e_mode<GEN>(P));
                     yv = (ACC)pick3(P.yI, slot)[t];
                 }
-                const ACC z = e2e_round(pw[j] * r + alpha * e2e_round(acc, P.e2e), P.e2e);
-                const ACC d = e2e_round(glm_delta<ACC>(z, yv, P.loss), P.e2e);
+                const int e2e = e2e_mode<GEN>(P);
+                const ACC z = e2e_round(pw[j] * r + alpha * e2e_round(acc, e2e), e2e);
+                const ACC d = e2e_round(glm_delta<ACC>(z, yv, loss_mode<GEN>(P)), e2e);
                 if (!isfinite(z) || !isfinite(d)) raise_flag(P.flags, FLAG_NONFINITE);
                 dl[t] = d;
-                c[t] = (float)e2e_round(pw[s - 1 - j] * d, P.e2e);
+                c[t] = (float)e2e_round(pw[s - 1 - j] * d, e2e);
                 if (delta_out) delta_out[t] = (float)d;
             }
         }

@@ -19,6 +19,7 @@ __device__ __forceinline__ void phase_mark(const Dense& P, int64_t hh, int k) {
 // Margins of outer iteration h from the slices' partial sums: eight lanes per
 // row, lane e adding slices e, e+8, ... in order, then a fixed tree over the
 // eight lanes; times the row scale. Threads gtid of nthreads (multiples of 8).
+template <bool GEN = true>
 __device__ __forceinline__ void reduce_margins(const Dense& P, const float* rp, uint64_t h,
                                                float* r_out, int gtid, int nthreads) {
     const float* sI = pick3(P.sI, slot_of(h));
@@ -31,21 +32,33 @@ __device__ __forceinline__ void reduce_margins(const Dense& P, const float* rp, 
         a += shfl_xor(a, 1);
         a += shfl_xor(a, 2);
         a += shfl_xor(a, 4);
-        if (e == 0) r_out[t] = e2e_round(a * sI[t], P.e2e);
+        if (e == 0) r_out[t] = e2e_round(a * sI[t], e2e_mode<GEN>(P));
     }
 }
 
 // The recurrence workgroup of rank `rank` (0 = chain, 1.. = helpers) for the
 // problem's b (16, 32, 64 or 128).
-template <typename ACC>
+template <typename ACC, bool GEN = true>
 __device__ __forceinline__ void rec_multi_rank(const Dense& P, const float* G, const float* r,
                                                const float* y, float* c, unsigned long long spin,
                                                unsigned char* lds, int rank) {
     switch (P.b) {
-        case 16: recurrence_multi<ACC, 1>(P, G, r, y, c, nullptr, P.pub, spin, lds, rank); break;
-        case 32: recurrence_multi<ACC, 2>(P, G, r, y, c, nullptr, P.pub, spin, lds, rank); break;
-        case 64: recurrence_multi<ACC, 4>(P, G, r, y, c, nullptr, P.pub, spin, lds, rank); break;
-        default: recurrence_multi<ACC, 8>(P, G, r, y, c, nullptr, P.pub, spin, lds, rank); break;
+        case 16:
+            recurrence_multi<ACC, 1, rec_window<1>(), GEN>(P, G, r, y, c, nullptr, P.pub, spin, lds,
+                                                          rank);
+            break;
+        case 32:
+            recurrence_multi<ACC, 2, rec_window<2>(), GEN>(P, G, r, y, c, nullptr, P.pub, spin, lds,
+                                                          rank);
+            break;
+        case 64:
+            recurrence_multi<ACC, 4, rec_window<4>(), GEN>(P, G, r, y, c, nullptr, P.pub, spin, lds,
+                                                          rank);
+            break;
+        default:
+            recurrence_multi<ACC, 8, rec_window<8>(), GEN>(P, G, r, y, c, nullptr, P.pub, spin, lds,
+                                                          rank);
+            break;
     }
 }
 
@@ -75,7 +88,7 @@ __host__ __device__ inline size_t fit_lds_bytes(int sb, int s, int acc_bytes, in
 //    gathers; one barrier (small s*b, plain SGD).
 //  * variant 2: workgroup 0 runs the single-workgroup recurrence while the
 //    others build the next Gram and gather; barrier; update; barrier.
-template <int DT, typename ACC, bool MULTI>
+template <int DT, typename ACC, bool MULTI, bool GEN = true>
 __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigned long long spin,
                                          unsigned char* lds) {
     constexpr int KW = slice_width<DT>();
@@ -104,9 +117,9 @@ __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigne
     gather_rows<DT>(P, h0, gw, ngw);
     if (H > 1) gather_rows<DT>(P, h0 + 1, gw, ngw);
     if (!grid_barrier(P.flags, wg, nb, spin)) return;
-    if (has_gram) gram_phase<DT>(P, P.G[0], h0, base, base + nb, lds);
+    if (has_gram) gram_phase<DT, GEN>(P, P.G[0], h0, base, base + nb, lds);
     for (int sl = wg; sl < P.nslices; sl += nb)
-        update_margin_slice<DT, kNW>(P, sl, nullptr, 0, false, h0, true, P.rp[0], red, xs, -1);
+        update_margin_slice<DT, kNW, GEN>(P, sl, nullptr, 0, false, h0, true, P.rp[0], red, xs, -1);
     if (!grid_barrier(P.flags, wg, nb, spin)) return;
     for (int64_t hh = 0; hh < H; ++hh) {
         const uint64_t h = h0 + (uint64_t)hh;
@@ -125,7 +138,7 @@ __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigne
                 // margins of h0 (from the prologue): reduced by the recurrence
                 // workgroups themselves
                 if (wg < nrec) {
-                    reduce_margins(P, pick2(P.rp, cur), h, P.r, wg * kNT + (int)threadIdx.x,
+                    reduce_margins<GEN>(P, pick2(P.rp, cur), h, P.r, wg * kNT + (int)threadIdx.x,
                                    nrec * kNT);
                     if (!barrier_at(P.flags, FLAG_BAR_SUB, wg, nrec, spin)) return;
                 }
@@ -136,14 +149,14 @@ __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigne
             const int units = P.g128 ? P.t128 : (P.gna == 4 ? P.gt : 2 * P.gt);
             const bool claim = (P.g128 || P.ksplit == 1) && units > nb - nrec;
             if (wg < nrec) {
-                rec_multi_rank<ACC>(P, pick2(P.G, cur), P.r, pick3(P.yI, slot_of(h)), P.c, spin, lds,
+                rec_multi_rank<ACC, GEN>(P, pick2(P.G, cur), P.r, pick3(P.yI, slot_of(h)), P.c, spin, lds,
                                     wg);
                 if (wg == 0) phase_mark(P, hh, 1);
             } else if (has_gram && more && !claim) {
-                gram_phase<DT>(P, pick2(P.G, nxt), h + 1, base + nrec, base + nb, lds);
+                gram_phase<DT, GEN>(P, pick2(P.G, nxt), h + 1, base + nrec, base + nb, lds);
             }
             if (has_gram && more && claim)
-                gram_claim<DT>(P, pick2(P.G, nxt), h + 1, P.flags + FLAG_GRAM_CLAIM + (hh & 1), lds);
+                gram_claim<DT, GEN>(P, pick2(P.G, nxt), h + 1, P.flags + FLAG_GRAM_CLAIM + (hh & 1), lds);
             if (wg == nrec) phase_mark(P, hh, 2);
             if (wg == nb - 1) phase_mark(P, hh, 6);
             if (!grid_barrier(P.flags, wg, nb, spin)) return;
@@ -162,7 +175,7 @@ __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigne
             // for the next phase.
             const bool split = nb > P.nslices;
             for (int sl = wg; sl < P.nslices; sl += nb)
-                update_margin_slice<DT, kNW>(P, sl, P.c, h, true, h + 1, more, pick2(P.rp, nxt), red,
+                update_margin_slice<DT, kNW, GEN>(P, sl, P.c, h, true, h + 1, more, pick2(P.rp, nxt), red,
                                              xs, snap_row);
             if (wg == 0) phase_mark(P, hh, 4);
             if (split && wg < P.nslices && more) {
@@ -182,7 +195,7 @@ __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigne
             if (split && wg >= P.nslices && more) {
                 const unsigned want = (unsigned)P.nslices * (unsigned)(hh + 1);
                 if (!wait_count(P.flags, FLAG_SLICES, want, spin)) return;
-                reduce_margins(P, pick2(P.rp, nxt), h + 1, P.r,
+                reduce_margins<GEN>(P, pick2(P.rp, nxt), h + 1, P.r,
                                (wg - P.nslices) * kNT + (int)threadIdx.x, (nb - P.nslices) * kNT);
             }
             if (wg == nb - 1) phase_mark(P, hh, 7);
@@ -190,35 +203,35 @@ __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigne
             if (wg == 0) phase_mark(P, hh, 5);
             if (!split && more) {
                 if (wg < nrec) {
-                    reduce_margins(P, pick2(P.rp, nxt), h + 1, P.r, wg * kNT + (int)threadIdx.x,
+                    reduce_margins<GEN>(P, pick2(P.rp, nxt), h + 1, P.r, wg * kNT + (int)threadIdx.x,
                                    nrec * kNT);
                     if (!barrier_at(P.flags, FLAG_BAR_SUB, wg, nrec, spin)) return;
                 }
             }
         } else if (P.variant == 1) {
             if (wg < P.nslices) {
-                recurrence<ACC, kNT>(P, pick2(P.G, cur), pick2(P.rp, cur), h, nullptr, nullptr, cl,
+                recurrence<ACC, kNT, GEN>(P, pick2(P.G, cur), pick2(P.rp, cur), h, nullptr, nullptr, cl,
                                      nullptr, dl, pw, tpr);
                 for (int sl = wg; sl < P.nslices; sl += nb)
-                    update_margin_slice<DT, kNW>(P, sl, cl, h, true, h + 1, more, pick2(P.rp, nxt),
+                    update_margin_slice<DT, kNW, GEN>(P, sl, cl, h, true, h + 1, more, pick2(P.rp, nxt),
                                                  red, xs, snap_row);
             }
-            if (has_gram && more) gram_phase<DT>(P, pick2(P.G, nxt), h + 1, base, base + nb, lds);
+            if (has_gram && more) gram_phase<DT, GEN>(P, pick2(P.G, nxt), h + 1, base, base + nb, lds);
             if (more2) gather_rows<DT>(P, h + 2, gw, ngw);
             if (!grid_barrier(P.flags, wg, nb, spin)) return;
         } else {
             if (wg == 0) {
-                recurrence<ACC, kNT>(P, pick2(P.G, cur), pick2(P.rp, cur), h, nullptr, nullptr, P.c,
+                recurrence<ACC, kNT, GEN>(P, pick2(P.G, cur), pick2(P.rp, cur), h, nullptr, nullptr, P.c,
                                      nullptr, dl, pw, tpr);
             } else {
                 const int gw1 = gw - kNW, ngw1 = ngw - kNW;
                 if (has_gram && more)
-                    gram_phase<DT>(P, pick2(P.G, nxt), h + 1, base + 1, base + nb, lds);
+                    gram_phase<DT, GEN>(P, pick2(P.G, nxt), h + 1, base + 1, base + nb, lds);
                 if (more2) gather_rows<DT>(P, h + 2, gw1, ngw1);
             }
             if (!grid_barrier(P.flags, wg, nb, spin)) return;
             for (int sl = wg; sl < P.nslices; sl += nb)
-                update_margin_slice<DT, kNW>(P, sl, P.c, h, true, h + 1, more, pick2(P.rp, nxt), red,
+                update_margin_slice<DT, kNW, GEN>(P, sl, P.c, h, true, h + 1, more, pick2(P.rp, nxt), red,
                                              xs, snap_row);
             if (!grid_barrier(P.flags, wg, nb, spin)) return;
         }
@@ -227,17 +240,36 @@ __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigne
     }
 }
 
-template <int DT, typename ACC>
+// Many problems in one cooperative launch: workgroup w runs problem
+// wgmap[w].x as member wgmap[w].y of that problem's group (table[p].gsize
+// workgroups, contiguous). Each problem keeps its own workspace and barrier.
+// GEN = false when every problem of the batch is plain (logistic, no
+// end-to-end rounding), as the single-problem fit compiles that case.
+template <int DT, bool GEN>
+__global__ __launch_bounds__(kNT) void k_fit_batch(const Dense* table, const int2* wgmap,
+                                                   unsigned long long spin) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int2 me = wgmap[blockIdx.x];
+    const Dense& P = table[__builtin_amdgcn_readfirstlane(me.x)];
+    const int wg = __builtin_amdgcn_readfirstlane(me.y);
+    if (P.recur64)
+        fit_body<DT, double, true, GEN>(P, wg, P.gsize, spin, lds);
+    else
+        fit_body<DT, float, true, GEN>(P, wg, P.gsize, spin, lds);
+}
+
+template <int DT, typename ACC, bool GEN>
 __global__ __launch_bounds__(kNT) void k_fit(Dense P, unsigned long long spin) {
     extern __shared__ __align__(16) unsigned char lds[];
-    fit_body<DT, ACC, true>(P, blockIdx.x, gridDim.x, spin, lds);
+    fit_body<DT, ACC, true, GEN>(P, blockIdx.x, gridDim.x, spin, lds);
 }
 
 
 template <int DT, typename ACC>
 inline casgd_status launch_fit_t(const Dense& P, const FitPlan& plan, hipStream_t st) {
     const size_t lds = fit_lds_bytes(P.sb, P.s, (int)sizeof(ACC), slice_width<DT>());
-    auto kern = k_fit<DT, ACC>;
+    // the default (logistic, no end-to-end rounding) without run-time mode branches
+    auto kern = (P.loss != 0 || P.e2e != 0) ? k_fit<DT, ACC, true> : k_fit<DT, ACC, false>;
     if (lds > 65536) {
         set_error("fused kernel needs %zu bytes of LDS (s*b too large for it)", lds);
         return CASGD_EUNSUPPORTED;
@@ -255,10 +287,16 @@ inline int fit_max_grid(const Dense& P) {
     const size_t lds = fit_lds_bytes(P.sb, P.s, (int)sizeof(ACC), slice_width<DT>());
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void*>(k_fit<DT, ACC>), kNT, lds) != hipSuccess)
+            &per_cu, reinterpret_cast<const void*>(k_fit<DT, ACC, false>), kNT, lds) != hipSuccess)
         return 0;
     return per_cu * device_cus();
 }
 
+
+template <int DT>
+inline const void* batch_kernel_t(bool generic) {
+    return generic ? reinterpret_cast<const void*>(k_fit_batch<DT, true>)
+                   : reinterpret_cast<const void*>(k_fit_batch<DT, false>);
+}
 
 }  // namespace casgd

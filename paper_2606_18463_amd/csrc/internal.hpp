@@ -74,12 +74,16 @@ casgd_status make_dense(const casgd_matrix* X, const float* y, float* x, double 
                         void* ws, size_t ws_bytes, Dense* P, DenseLayout* L, bool need_ws);
 casgd_status run_zero(unsigned* p, int64_t words, hipStream_t st);
 casgd_status run_fit_batch(const Dense* table_dev, const int2* wgmap_dev, int grid, int dtype,
-                           size_t lds, unsigned long long spin, hipStream_t st);
-int batch_max_grid(int dtype, size_t lds);
+                           size_t lds, unsigned long long spin, bool generic, hipStream_t st);
+int batch_max_grid(int dtype, size_t lds, bool generic);
 casgd_status launch_fit_f32(const Dense& P, const FitPlan& plan, hipStream_t st);
 casgd_status launch_fit_bf16(const Dense& P, const FitPlan& plan, hipStream_t st);
 casgd_status launch_fit_f16(const Dense& P, const FitPlan& plan, hipStream_t st);
 casgd_status launch_fit_fp8(const Dense& P, const FitPlan& plan, hipStream_t st);
+const void* batch_kernel_f32(bool generic);
+const void* batch_kernel_bf16(bool generic);
+const void* batch_kernel_f16(bool generic);
+const void* batch_kernel_fp8(bool generic);
 int fit_max_grid_f32(const Dense& P, int recur64);
 int fit_max_grid_bf16(const Dense& P, int recur64);
 int fit_max_grid_f16(const Dense& P, int recur64);

@@ -3,8 +3,8 @@
 // allocate device memory. Same kernels and launch plan as casgd_fit.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstring>
-#include <mutex>
 
 #include "internal.hpp"
 
@@ -19,8 +19,9 @@ static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 // The device address of `scratch` on each device, looked up once per device
 // with that device current (the host-side symbol is not a device address).
-static std::mutex g_scratch_mu;
-static void* g_scratch_ptr[64];
+// Atomic slots (no lock, nothing to destroy at exit): concurrent first calls
+// on one device look the address up twice and store the same value.
+static std::atomic<void*> g_scratch_ptr[64];
 
 static casgd_status scratch_ptr(void** out) {
     int dev = 0;
@@ -29,17 +30,16 @@ static casgd_status scratch_ptr(void** out) {
         set_error("device index %d out of range", dev);
         return CASGD_EUNSUPPORTED;
     }
-    std::lock_guard<std::mutex> g(g_scratch_mu);
-    if (!g_scratch_ptr[dev]) {
-        void* p = nullptr;
+    void* p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+    if (!p) {
         CASGD_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
         if (!p) {
             set_error("hipGetSymbolAddress returned a null address for the scratch array");
             return CASGD_EDEVICE;
         }
-        g_scratch_ptr[dev] = p;
+        g_scratch_ptr[dev].store(p, std::memory_order_release);
     }
-    *out = g_scratch_ptr[dev];
+    *out = p;
     return CASGD_OK;
 }
 

@@ -105,7 +105,7 @@ __host__ __device__ inline int rec_helpers(int b, int s) {
 // every column block), 64 rows per pass. r: reduced margins (row scales
 // applied); y: labels; c, delta_out: outputs; pub: 2 * sb * pub_words
 // tagged words (deltas, then far sums).
-template <typename ACC, int NV, int W = rec_window<NV>()>
+template <typename ACC, int NV, int W = rec_window<NV>(), bool GEN = true>
 __device__ void recurrence_multi(const Dense& P, const float* G, const float* r, const float* y,
                                  float* c, float* delta_out, unsigned long long* pub,
                                  unsigned long long spin, unsigned char* lds, int rank) {
@@ -193,12 +193,12 @@ __device__ void recurrence_multi(const Dense& P, const float* G, const float* r,
                 if (sub == 0 && q < b) {
                     const int t = j * b + q;
                     const ACC rv = (ACC)ry[p].x, yv = (ACC)ry[p].y;
-                    const ACC z = e2e_round(pw[j] * rv + alpha * e2e_round(far + nsum, P.e2e),
-                                            P.e2e);
-                    const ACC d = e2e_round(glm_delta<ACC>(z, yv, P.loss), P.e2e);
+                    const int e2e = e2e_mode<GEN>(P);
+                    const ACC z = e2e_round(pw[j] * rv + alpha * e2e_round(far + nsum, e2e), e2e);
+                    const ACC d = e2e_round(glm_delta<ACC>(z, yv, loss_mode<GEN>(P)), e2e);
                     if (!isfinite(z) || !isfinite(d)) raise_flag(P.flags, FLAG_NONFINITE);
                     dl[t] = d;
-                    c[t] = (float)e2e_round(pw[s - 1 - j] * d, P.e2e);
+                    c[t] = (float)e2e_round(pw[s - 1 - j] * d, e2e);
                     if (delta_out) delta_out[t] = (float)d;
                     if (j < R) pub_put(dpub + (size_t)t * PW, d);
                 }

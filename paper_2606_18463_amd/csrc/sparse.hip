@@ -3,8 +3,6 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
-#include <map>
-#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -141,7 +139,7 @@ namespace {
 struct SparseLayout {
     int sb, sbpad, maxlen, L;
     DenseLayout gl;  // Gram tiles over the head panel (n = kHeadMax, FP32)
-    size_t off_flags, off_tilecnt, off_G0, off_G1, off_Gpart, off_r, off_c, off_pub, off_lbeta, off_lbs,
+    size_t off_flags, off_prep, off_tilecnt, off_G0, off_G1, off_Gpart, off_r, off_c, off_pub, off_lbeta, off_lbs,
         off_headid, off_headcol, off_colcnt, off_Yh[3], off_tcol[3], off_tval[3], off_tlen[3],
         off_yI[3], off_bcnt[2], off_bent[2], off_tlist[2], off_tlcnt, total;
 };
@@ -158,6 +156,7 @@ void sparse_layout(int64_t n, int b, int s, int L, int maxlen, SparseLayout* S) 
     size_t off = 0;
     auto take = [&](size_t& o, size_t bytes) { o = off; off = a256(off + bytes); };
     take(S->off_flags, FLAG_WORDS * 4);
+    take(S->off_prep, 256);   // the Prepared record (fixed offset: flags come first)
     take(S->off_tilecnt, (size_t)S->gl.ntiles * 2 * 4);
     take(S->off_G0, sb * sb * 4);
     take(S->off_G1, sb * sb * 4);
@@ -186,16 +185,20 @@ void sparse_layout(int64_t n, int b, int s, int L, int maxlen, SparseLayout* S) 
     S->total = off;
 }
 
+// What casgd_sparse_prepare decided for a workspace (X, b, s, lanes, the
+// head split), stored in the workspace itself right after the flag words:
+// the library keeps no host state between calls.
 struct Prepared {
+    uint64_t magic;
     const void* rp;
     const void* ci;
     const void* va;
     int64_t m, n, nnz;
     int b, s, L, H, Hp, maxlen;
 };
-
-std::mutex g_mu;
-std::map<const void*, Prepared> g_prep;
+constexpr uint64_t kPrepMagic = 0x63617367645f7370ull;   // "casgd_sp"
+constexpr size_t kPrepOffset = (FLAG_WORDS * 4 + 255) & ~(size_t)255;
+static_assert(sizeof(Prepared) <= 256, "the prepared record has 256 bytes");
 
 casgd_status csr_maxlen(const casgd_matrix* X, int* maxlen) {
     std::vector<int64_t> rp((size_t)X->m + 1);
@@ -301,18 +304,17 @@ casgd_status sparse_prepare(const casgd_matrix* X, int32_t b, int32_t s, int32_t
         head_id[sel[i]] = i;
         head_col[i] = sel[i];
     }
-    CASGD_HIP(hipMemcpy(at<int32_t>(ws, SL.off_headid), head_id.data(), head_id.size() * 4,
-                        hipMemcpyHostToDevice));
-    CASGD_HIP(hipMemcpy(at<int32_t>(ws, SL.off_headcol), head_col.data(), head_col.size() * 4,
-                        hipMemcpyHostToDevice));
+    CASGD_HIP(hipMemcpyAsync(at<int32_t>(ws, SL.off_headid), head_id.data(), head_id.size() * 4,
+                             hipMemcpyHostToDevice, st));
+    CASGD_HIP(hipMemcpyAsync(at<int32_t>(ws, SL.off_headcol), head_col.data(),
+                             head_col.size() * 4, hipMemcpyHostToDevice, st));
     for (int k = 0; k < 2; ++k)
-        CASGD_HIP(hipMemset(at<unsigned>(ws, SL.off_bcnt[k]), 0, (size_t)X->n * 4));
-    CASGD_HIP(hipMemset(ws, 0, FLAG_WORDS * 4));
-    CASGD_HIP(hipDeviceSynchronize());
-    Prepared P{X->row_ptr, X->col_idx, X->values, X->m, X->n, X->nnz, b, s, lanes, H,
-               (H + 127) / 128 * 128, maxlen};
-    std::lock_guard<std::mutex> g(g_mu);
-    g_prep[ws] = P;
+        CASGD_HIP(hipMemsetAsync(at<unsigned>(ws, SL.off_bcnt[k]), 0, (size_t)X->n * 4, st));
+    CASGD_HIP(hipMemsetAsync(ws, 0, FLAG_WORDS * 4, st));
+    const Prepared P{kPrepMagic, X->row_ptr, X->col_idx, X->values, X->m, X->n, X->nnz, b, s,
+                     lanes, H, (H + 127) / 128 * 128, maxlen};
+    CASGD_HIP(hipMemcpyAsync(at<char>(ws, SL.off_prep), &P, sizeof P, hipMemcpyHostToDevice, st));
+    CASGD_HIP(hipStreamSynchronize(st));
     return CASGD_OK;
 }
 
@@ -335,15 +337,17 @@ casgd_status sparse_fit(const casgd_matrix* X, const float* y, float* x_lanes,
             set_error("lambda[%d] must be finite and >= 0", l);
             return CASGD_EINVAL;
         }
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) || ws_bytes < kPrepOffset + 256) {
+        set_error("workspace missing, misaligned or too small");
+        return CASGD_EINVAL;
+    }
+    // the record casgd_sparse_prepare left in the workspace (written once,
+    // before that call returned; a small synchronous read)
     Prepared P;
-    {
-        std::lock_guard<std::mutex> g(g_mu);
-        auto it = g_prep.find(ws);
-        if (it == g_prep.end()) {
-            set_error("workspace not prepared: call casgd_sparse_prepare for this X, b, s first");
-            return CASGD_EINVAL;
-        }
-        P = it->second;
+    CASGD_HIP(hipMemcpy(&P, at<char>(ws, kPrepOffset), sizeof P, hipMemcpyDeviceToHost));
+    if (P.magic != kPrepMagic) {
+        set_error("workspace not prepared: call casgd_sparse_prepare for this X, b, s first");
+        return CASGD_EINVAL;
     }
     if (P.rp != X->row_ptr || P.ci != X->col_idx || P.va != X->values || P.m != X->m ||
         P.n != X->n || P.b != b || P.s != s || L > P.L) {
