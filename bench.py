@@ -153,7 +153,7 @@ GRAM_SHAPES = [(1 << 20, 2048, 64, 16), (1 << 20, 2048, 64, 32), (4096, 256, 128
                (8192, 16384, 32, 32), (8192, 16384, 32, 64), (8192, 16384, 32, 128)]
 
 
-def gram_shapes_bench(cg, dtypes, reps=10):
+def gram_shapes_bench(cg, dtypes, reps=10, shapes=None):
     """Standalone Gram launches (casgd_gram_margin without margins: one
     counter-clearing, one gather and one Gram launch per call) at the roofline
     shapes, for each storage type. Timed with HIP events per call (gather
@@ -161,7 +161,7 @@ def gram_shapes_bench(cg, dtypes, reps=10):
     import torch
     stream = torch.cuda.current_stream()
     rows = []
-    for (m, n, b, s) in GRAM_SHAPES:
+    for (m, n, b, s) in (shapes or GRAM_SHAPES):
         g = torch.Generator(device="cuda")
         g.manual_seed(m * 7 + n)
         X32 = torch.randn(m, n, device="cuda", generator=g) * (1.0 / math.sqrt(n))
@@ -241,22 +241,44 @@ def e2e_study(cg, H: int = 320_000, snaps: int = 64):
             "outer_iterations": snaps * every, "snapshots": snaps, "recipes": rows}
 
 
-def cpu_baseline(wl: Workload, b, s, eta, lam, budget_s=15.0):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl: Workload, b, s, eta, lam, budget_s=12.0, budget1_s=8.0):
     """The FP64 oracle (as it stands) on the host cores: outer iterations of the
-    same workload until about `budget_s` seconds have been spent."""
+    same workload until about `budget_s` seconds have been spent with every
+    thread the oracle uses, then about `budget1_s` seconds on one thread."""
     from oracle import reference as R
-    x = np.zeros(wl.n)
-    t = time.perf_counter()
-    x = R.casgd(wl.p.X, wl.p.y, x, eta, lam, b, s, SEED, 0, 1)
-    t1 = time.perf_counter() - t
-    k = max(1, min(10_000, int(budget_s / max(t1, 1e-6))))
-    t = time.perf_counter()
-    R.casgd(wl.p.X, wl.p.y, x, eta, lam, b, s, SEED, 1, k)
-    dt = time.perf_counter() - t
-    return {"value": round(s * k / dt, 2), "unit": "SGD updates/s", "cores": R.threads(),
-            "kind": "oracle",
+
+    def run(budget):
+        x = np.zeros(wl.n)
+        t = time.perf_counter()
+        x = R.casgd(wl.p.X, wl.p.y, x, eta, lam, b, s, SEED, 0, 1)
+        t1 = time.perf_counter() - t
+        k = max(1, min(10_000, int(budget / max(t1, 1e-6))))
+        t = time.perf_counter()
+        R.casgd(wl.p.X, wl.p.y, x, eta, lam, b, s, SEED, 1, k)
+        return k, time.perf_counter() - t
+
+    cores = R.threads()
+    k, dt = run(budget_s)
+    R.set_threads(1)
+    k1, dt1 = run(budget1_s)
+    R.set_threads(cores)
+    return {"value": round(s * k / dt, 2), "unit": "SGD updates/s", "cores": cores,
+            "kind": "oracle", "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "single_thread_value": round(s * k1 / dt1, 2),
             "sample": f"{k} outer iterations (b={b}, s={s}) of the 2^20x2048 workload, "
-                      f"FP64 C oracle, {dt:.1f}s"}
+                      f"FP64 C oracle, {dt:.1f}s on {cores} threads; {k1} outer iterations, "
+                      f"{dt1:.1f}s on one thread"}
 
 
 def eta_sweep(cg, wl: Workload, etas):
@@ -690,6 +712,10 @@ def main():
                     help="uneven problems at full size: batched vs one launch per problem")
     ap.add_argument("--gram-shapes", action="store_true",
                     help="standalone Gram launches at the roofline shapes (all storage types)")
+    ap.add_argument("--gram-dtype", default=None, choices=list(DT_NAME),
+                    help="with --gram-shapes: only this storage type")
+    ap.add_argument("--gram-shape", type=int, default=None,
+                    help="with --gram-shapes: only this index of the shape list")
     ap.add_argument("--e2e-study", action="store_true",
                     help="long-horizon test-loss gap of the precision recipes to FP32")
     ap.add_argument("--c5-train", type=int, default=256)
@@ -720,7 +746,9 @@ def main():
         print(json.dumps(e2e_study(cg, H)), flush=True)
         return
     if args.gram_shapes:
-        print(json.dumps(gram_shapes_bench(cg, ["f32", "bf16", "fp8"])), flush=True)
+        dts = [args.gram_dtype] if args.gram_dtype else ["f32", "bf16", "fp8"]
+        shapes = [GRAM_SHAPES[args.gram_shape]] if args.gram_shape is not None else GRAM_SHAPES
+        print(json.dumps(gram_shapes_bench(cg, dts, shapes=shapes)), flush=True)
         return
     if args.c5_batch:
         H = args.steps if args.steps is not None else 32

@@ -627,3 +627,14 @@ int oracle_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the parallel loops from now on (timing the oracle on one core). */
+void oracle_set_threads(int32_t nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+}

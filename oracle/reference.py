@@ -120,6 +120,8 @@ def lib():
         L.oracle_casgd_csr_glm.restype = ctypes.c_int
         L.oracle_casgd_csr_glm.argtypes = [_pi64, _pi32, _pd, _i64, _i64, _pd, _pd, _dbl,
                                            _dbl, _i32, _i32, _u64, _u64, _i64, _i32]
+        L.oracle_set_threads.restype = None
+        L.oracle_set_threads.argtypes = [_i32]
         L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_num_threads.argtypes = []
         _lib = L
@@ -163,6 +165,11 @@ def sample_indices(seed: int, t0: int, count: int, m: int) -> np.ndarray:
 
 def threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on."""
+    lib().oracle_set_threads(int(n))
 
 
 # ------------------------------------------------------------------ solvers
