@@ -174,27 +174,33 @@ def gram_shapes_bench(cg, dtypes, reps=10, shapes=None):
                 X = cg.dense_matrix(keep[0], keep[1], n=n)
             sb = s * b
             G = torch.empty(sb, sb, device="cuda")
-            ws = cg.workspace(cg.casgd_workspace_size(X, b, s))
-            for tile in (64, 128):
+            base = cg.casgd_workspace_size(X, b, s)
+            split = cg.casgd_gram_workspace_size(X, b, s)
+            ws = cg.workspace(split)
+            kinds = [(64, base), (128, base)] + ([(128, split)] if split > base else [])
+            for tile, nb in kinds:
                 o = cg.opts(gram_tile=tile)
+                ksplit = nb > base
+                wsv = ws[:nb]
                 for h in range(2):
-                    cg.casgd_gram_margin(X, None, b, s, SEED, h, G=G, ws=ws, stream=stream, opts=o)
+                    cg.casgd_gram_margin(X, None, b, s, SEED, h, G=G, ws=wsv, stream=stream, opts=o)
                 torch.cuda.synchronize()
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
                 for h in range(reps):
-                    cg.casgd_gram_margin(X, None, b, s, SEED, h, G=G, ws=ws, stream=stream, opts=o)
+                    cg.casgd_gram_margin(X, None, b, s, SEED, h, G=G, ws=wsv, stream=stream, opts=o)
                 e1.record(stream)
                 torch.cuda.synchronize()
                 us = e0.elapsed_time(e1) * 1e3 / reps
                 fl = gram_flops(b, s, n)
                 rows.append({"m": m, "n": n, "b": b, "s": s, "storage": dt, "gram_tile": tile,
-                             "us_per_call_with_gather": round(us, 3),
+                             "k_split": ksplit, "us_per_call_with_gather": round(us, 3),
                              "gram_flops": fl, "paper_flops": 2.0 * sb * sb * n})
-                log(f"[gram] m={m} n={n} b={b} s={s} {dt} tile {tile}: {us:.2f} us per call "
+                log(f"[gram] m={m} n={n} b={b} s={s} {dt} tile {tile}"
+                    f"{' split along K' if ksplit else ''}: {us:.2f} us per call "
                     f"({fl / (us * 1e-6) / 1e12:.1f} TFLOP/s incl. gather)")
-            del G, ws, X, keep
+            del G, ws, wsv, X, keep
         del X32
         torch.cuda.empty_cache()
     return {"metric": "standalone Gram launches at the roofline shapes", "rows": rows}

@@ -346,8 +346,24 @@ casgd_status casgd_sample_indices(uint64_t seed, uint64_t t0, int64_t count, int
  * block(u) < block(t), written; other entries are left untouched. x and r
  * may both be NULL to compute the Gram alone. opts (may be NULL): gram_tile
  * selects the Gram unit kind as for a fit (automatic: 128 x 128 tiles when
- * there are at least as many as compute units).
+ * there are at least as many as compute units). With a workspace of
+ * casgd_gram_workspace_size bytes, 128 x 128 tiles are split along K over
+ * several workgroups when the device holds more workgroups than there are
+ * tiles (or than the tiles left after whole rounds), for rows of 8 KB or
+ * more: a cooperative launch; the pieces' sums are added in a fixed order,
+ * so the result is reproducible. The automatic kind is then the split
+ * 128 x 128 tiles for rows of 16 KB or more. With casgd_workspace_size
+ * bytes no tile is split.
  */
+casgd_status casgd_gram_workspace_size(const casgd_matrix *X, int32_t b, int32_t s,
+                                       size_t *bytes);
+/* casgd_gram_workspace_size: workspace bytes of casgd_gram_margin (and of
+ * stream-ordered fits, exec_mode 2) that include the exchange region of the
+ * K-split Gram: casgd_workspace_size plus, when the split applies to this
+ * shape, an epoch word and one 128 x 128 slot of 64-bit words per piece. The
+ * region must be zero when the workspace is first used (a zero-filled
+ * allocation) and is never cleared by the library: each launch tags its words
+ * with a new epoch. Dense X only. */
 casgd_status casgd_gram_margin(const casgd_matrix *X, const float *x, int32_t b,
                                int32_t s, uint64_t seed, uint64_t outer_iter, float *G,
                                float *r, const casgd_opts *opts, void *ws, size_t ws_bytes,

@@ -16,8 +16,8 @@ from ._lib import LOSS_LINEAR, LOSS_LOGISTIC, LOSS_POISSON, LOSSES  # noqa: F401
 
 __all__ = [
     "CasgdError", "dense_matrix", "csr_matrix", "opts", "workspace",
-    "casgd_workspace_size", "casgd_reset", "casgd_step", "casgd_fit", "casgd_check",
-    "casgd_fit_noalloc",
+    "casgd_workspace_size", "casgd_gram_workspace_size", "casgd_reset", "casgd_step", "casgd_fit",
+    "casgd_check", "casgd_fit_noalloc",
     "casgd_sample_indices", "casgd_gram_margin", "casgd_recurrence", "casgd_update",
     "casgd_quantize", "casgd_logloss", "casgd_loss", "casgd_colstats", "casgd_version",
     "casgd_recurrence_workspace_size",
@@ -264,14 +264,22 @@ def casgd_sample_indices(seed: int, t0: int, count: int, m: int, out=None, strea
     return out
 
 
+def casgd_gram_workspace_size(X: MatrixRef, b: int, s: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(_L().casgd_gram_workspace_size(X.ref(), b, s, ctypes.byref(out)))
+    return int(out.value)
+
+
 def casgd_gram_margin(X: MatrixRef, x, b: int, s: int, seed: int, outer_iter: int, G=None,
                       r=None, ws=None, stream=None, opts=None):
+    """Margins and Gram of one outer iteration. The workspace (zero-filled when
+    allocated here) holds the K-split Gram's exchange region."""
     torch = _torch()
     sb = s * b
     G = G if G is not None else torch.zeros(sb, sb, dtype=torch.float32, device="cuda")
     if x is not None and r is None:
         r = torch.zeros(sb, dtype=torch.float32, device="cuda")
-    ws, nb = _ws(ws, casgd_workspace_size(X, b, s))
+    ws, nb = _ws(ws, casgd_gram_workspace_size(X, b, s))
     _check(_L().casgd_gram_margin(X.ref(), _ptr(x), b, s, seed, outer_iter, _ptr(G), _ptr(r),
                                   _opts_ref(opts), _ptr(ws), nb, _stream(stream)))
     return G, r

@@ -75,6 +75,7 @@ SIGNATURES = {
     "casgd_last_error": (ctypes.c_char_p, []),
     "casgd_version": (c_i32, []),
     "casgd_workspace_size": (c_i32, [PM, c_i32, c_i32, ctypes.POINTER(c_sz)]),
+    "casgd_gram_workspace_size": (c_i32, [PM, c_i32, c_i32, ctypes.POINTER(c_sz)]),
     "casgd_reset": (c_i32, [c_vp, c_sz, c_vp]),
     "casgd_step": (c_i32, [PM, c_vp, c_vp, c_dbl, c_dbl, c_i32, c_i32, c_u64, c_u64, PO, c_vp,
                            c_sz, c_vp]),

@@ -144,10 +144,25 @@ bool dense_layout(int64_t n, int dtype, int b, int s, DenseLayout* L) {
         off = align256(off + (size_t)sb * 4);
     }
     L->total = off;
+    // K-split region of the stand-alone 128-tile Gram (two workgroups per CU
+    // resident): the tiles left after whole rounds of that many, split into
+    // pieces of at least 16 K chunks of 128 bytes, at most 16 per tile; only
+    // for rows of 64 chunks or more (with shorter rows the exchange costs
+    // about as much as a piece: measured slower than whole tiles)
+    {
+        const int64_t nch = (n * dtype_bytes(dtype) + kChunkB - 1) / kChunkB;
+        const int R = 2 * ncu, Tn = L->t128;
+        const int rem = R <= 0 ? 0 : (Tn <= R ? Tn : Tn % R);
+        int64_t S = 0;
+        if (s > 1 && L->n128 > 0 && rem > 0 && nch >= 64)
+            S = std::min<int64_t>({16, nch / 16, R / rem});
+        L->sk_nslots = S >= 2 ? (int)(rem * S) : 0;
+        L->total_sk = L->sk_nslots ? off + 256 + (size_t)L->sk_nslots * kGramSkWords * 8 : off;
+    }
     return true;
 }
 
-void dense_bind(const DenseLayout& L, void* ws, Dense* P) {
+void dense_bind(const DenseLayout& L, void* ws, size_t ws_bytes, Dense* P) {
     char* w = static_cast<char*>(ws);
     P->sb = L.sb;
     P->ts = L.ts;
@@ -176,6 +191,14 @@ void dense_bind(const DenseLayout& L, void* ws, Dense* P) {
         P->Y[k] = w + L.off_Y[k];
         P->yI[k] = reinterpret_cast<float*>(w + L.off_yI[k]);
         P->sI[k] = reinterpret_cast<float*>(w + L.off_sI[k]);
+    }
+    P->sk_nslots = 0;
+    P->sk_epoch = nullptr;
+    P->sk_slots = nullptr;
+    if (L.sk_nslots && ws_bytes >= L.total_sk) {
+        P->sk_nslots = L.sk_nslots;
+        P->sk_epoch = reinterpret_cast<unsigned*>(w + L.total);
+        P->sk_slots = reinterpret_cast<unsigned long long*>(w + L.total + 256);
     }
 }
 
@@ -312,7 +335,7 @@ casgd_status make_dense(const casgd_matrix* X, const float* y, float* x, double 
     P->beta = (float)P->beta_d;
     P->beta_s = (float)std::pow(P->beta_d, (double)s);
     if (need_ws) {
-        dense_bind(*L, ws, P);
+        dense_bind(*L, ws, ws_bytes, P);
     } else {
         P->sb = L->sb;
         P->ts = L->ts;
@@ -378,6 +401,21 @@ const char* casgd_status_string(casgd_status st) {
 const char* casgd_last_error(void) { return t_err; }
 
 int32_t casgd_version(void) { return 100; }
+
+casgd_status casgd_gram_workspace_size(const casgd_matrix* X, int32_t b, int32_t s,
+                                       size_t* bytes) {
+    casgd_status rc;
+    if (!bytes) {
+        set_error("bytes is NULL");
+        return CASGD_EINVAL;
+    }
+    if ((rc = check_dense(X)) != CASGD_OK) return rc;
+    if ((rc = check_bs(b, s)) != CASGD_OK) return rc;
+    DenseLayout L;
+    dense_layout(X->n, X->dtype, b, s, &L);
+    *bytes = L.total_sk;
+    return CASGD_OK;
+}
 
 casgd_status casgd_workspace_size(const casgd_matrix* X, int32_t b, int32_t s, size_t* bytes) {
     casgd_status rc;
@@ -692,7 +730,12 @@ casgd_status casgd_gram_margin(const casgd_matrix* X, const float* x, int32_t b,
         set_error("gram_tile must be 0, 64 or 128 (got %d)", gram_tile);
         return CASGD_EINVAL;
     }
-    P.g128 = choose_gram128(P, X->dtype, gram_tile, device_cus());
+    // automatic: the K-split 128-tiles for long rows (128 chunks of 128 bytes
+    // or more) when the workspace holds their region; otherwise the rule of
+    // the fits
+    const int64_t nch = (X->n * dtype_bytes(X->dtype) + kChunkB - 1) / kChunkB;
+    P.g128 = (gram_tile == 0 && P.sk_nslots > 0 && nch >= 128) ||
+             choose_gram128(P, X->dtype, gram_tile, device_cus());
     hipStream_t st = (hipStream_t)stream;
     if ((rc = run_zero(P.tile_cnt, 2 * P.ntiles, st)) != CASGD_OK) return rc;
     if ((rc = run_gather(P, X->dtype, outer_iter, st)) != CASGD_OK) return rc;

@@ -39,11 +39,59 @@ __global__ __launch_bounds__(kNT) void k_gram(Dense P, float* Gout, uint64_t h) 
     gram_phase<DT>(P, Gout, h, 0, gridDim.x, lds);
 }
 
-// One 128 x 128 LDS tile per workgroup.
+// One 128 x 128 LDS tile per workgroup. With a long K range (16 chunks or
+// more) the tiles are dealt so that each XCD takes a contiguous run of the
+// grouped tile order (workgroup i runs on XCD i % 8): the tiles that run on
+// one XCD at the same time then share their row panels in its L2. With a
+// short K range the panels are small and the tiles go in row order, which
+// measured faster there (consecutive workgroups store neighbouring tiles).
 template <int DT>
 __global__ __launch_bounds__(kNT) void k_gram128(Dense P, float* Gout, uint64_t h) {
+    using T = typename Store<DT>::T;
     __shared__ __align__(16) unsigned char lds[kGram128Lds];
-    gram_tile128<DT>(P, Gout, h, blockIdx.x, lds);
+    const int64_t nch = (P.n * (int64_t)sizeof(T) + kChunkB - 1) / kChunkB;
+    if (nch < 16) {
+        gram_tile128<DT>(P, Gout, h, blockIdx.x, lds);
+        return;
+    }
+    const int Tn = P.t128, id = blockIdx.x, x = id & 7;
+    const int L = x * (Tn >> 3) + min(x, Tn & 7) + (id >> 3);
+    int TJ, TI;
+    grouped_tile128(L, tiles128_per_side(P.sb), TJ, TI);
+    gram_tile128_at<DT>(P, Gout, h, TJ, TI, lds);
+}
+
+// The 128-tile Gram with K-split tiles, all workgroups resident (a
+// cooperative launch of G workgroups, XCD-grouped as above). Tiles 0 .. Tw-1
+// of the grouped order are computed whole, G at a time; each of the other
+// t128 - Tw tiles is split into S pieces, one per workgroup, after that.
+template <int DT>
+__global__ __launch_bounds__(kNT) void k_gram128_sk(Dense P, float* Gout, uint64_t h, int Tw,
+                                                    int S, unsigned long long spin) {
+    __shared__ __align__(16) unsigned char lds[kGram128Lds];
+    const unsigned tag = *P.sk_epoch;
+    const int G = gridDim.x, id = blockIdx.x, x = id & 7;
+    const int v = x * (G >> 3) + min(x, G & 7) + (id >> 3);
+    const int NT = tiles128_per_side(P.sb);
+    int TJ, TI;
+    for (int j = v; j < Tw; j += G) {
+        grouped_tile128(j, NT, TJ, TI);
+        gram_tile128_at<DT>(P, Gout, h, TJ, TI, lds);
+    }
+    if (v < (P.t128 - Tw) * S) {
+        const int r = v / S, p = v - r * S;
+        grouped_tile128(Tw + r, NT, TJ, TI);
+        gram_tile128_piece<DT>(P, Gout, h, TJ, TI, p, S,
+                               P.sk_slots + (size_t)r * S * kGramSkWords, tag, spin, lds);
+    }
+}
+
+// Next launch tag of the K-split Gram (never 0, the tag of a cleared word).
+__global__ void k_sk_epoch(unsigned* e) {
+    if (threadIdx.x == 0) {
+        const unsigned v = e[0] + 1u;
+        e[0] = v ? v : 1u;
+    }
 }
 
 template <int DT>
@@ -102,6 +150,30 @@ casgd_status launch_gather_reduce_t(const Dense& P, uint64_t h, int do_gather, c
 template <int DT>
 casgd_status launch_gram_t(const Dense& P, float* Gout, uint64_t h, hipStream_t st) {
     if (P.gt == 0 || P.s < 2) return CASGD_OK;
+    if (P.g128 && P.sk_nslots > 0) {
+        // every workgroup resident (the pieces of a tile wait for each other):
+        // with more tiles than that, whole rounds first, then the remainder
+        // split; pieces keep at least 16 K chunks, at most 16 per tile
+        using T = typename Store<DT>::T;
+        int per_cu = 0;
+        CASGD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gram128_sk<DT>, kNT, 0));
+        const int R = per_cu * device_cus(), Tn = P.t128;
+        const int rem = Tn <= R ? Tn : Tn % R;
+        const int nch = (int)((P.n * (int64_t)sizeof(T) + kChunkB - 1) / kChunkB);
+        const int S = rem > 0 ? std::min({16, nch / 16, R / rem, P.sk_nslots / rem}) : 0;
+        if (S >= 2) {
+            hipLaunchKernelGGL(k_sk_epoch, dim3(1), dim3(64), 0, st, P.sk_epoch);
+            CASGD_HIP(hipGetLastError());
+            Dense Pc = P;
+            int Tw = Tn - rem, Sv = S;
+            unsigned long long spin = 1ull << 24;
+            const int grid = Tn <= R ? rem * S : R;
+            void* args[] = {&Pc, &Gout, &h, &Tw, &Sv, &spin};
+            CASGD_HIP(hipLaunchCooperativeKernel((const void*)k_gram128_sk<DT>, dim3(grid),
+                                                 dim3(kNT), args, 0, st));
+            return CASGD_OK;
+        }
+    }
     if (P.g128) {
         hipLaunchKernelGGL(k_gram128<DT>, dim3(P.t128), dim3(kNT), 0, st, P, Gout, h);
         CASGD_HIP(hipGetLastError());

@@ -66,6 +66,10 @@ struct Dense {
     int e2e;                // E2E_* end-to-end low-precision emulation
     int g128;               // Gram units are 128 x 128 LDS tiles (gram_tile128)
     int t128;               // lower-triangular 128-tiles enumerated
+    // stand-alone 128-tile Gram split along K (gram_tile128_piece), or null
+    unsigned long long* sk_slots; // sk_nslots partial slots of kBig * kBig words
+    unsigned* sk_epoch;     // the launch tag, advanced before every such launch
+    int sk_nslots;          // 0: no K split
 };
 
 // The residual formula and the end-to-end rounding mode of a problem. GEN =
@@ -412,36 +416,81 @@ __device__ __forceinline__ void gram_unit(const Dense& P, float* Gout, uint64_t 
 // the reuse of a 64-row unit whose waves read their operands directly). A
 // single LDS buffer with register prefetch: the global loads of chunk c+1
 // are issued before the MFMAs of chunk c and written to LDS after them;
-// barriers order LDS only, so the loads stay in flight across them. Row
-// pitch 144 bytes: the 16 rows a 16-lane group reads start on distinct
-// banks. Rows are zero-padded to a multiple of 128 and to whole chunks of K.
+// barriers order LDS only, so the loads stay in flight across them. Rows
+// are zero-padded to a multiple of 128 and to whole chunks of K.
+// LDS layout: row r of a panel at r * 128 bytes, its 16-byte K segment k at
+// slot k ^ swz(r). The operand reads (16 consecutive rows, one segment) and
+// the staging writes (two rows, all eight segments) then touch 16 distinct
+// 16-byte bank groups, with 64 banks and with 32.
 constexpr int kBig = 128;                  // tile edge
 constexpr int kChunkB = 128;               // bytes of K per row per chunk
-constexpr int kRowB = kChunkB + 16;        // LDS row pitch
+constexpr int kRowB = kChunkB;             // LDS row pitch
 constexpr size_t kGram128Lds = 2 * (size_t)kBig * kRowB;
+
+__device__ __forceinline__ int swz128(int r) { return ((r >> 1) & 7) ^ ((r & 1) << 2); }
 
 __host__ __device__ inline int tiles128_per_side(int sb) { return (sb + kBig - 1) / kBig; }
 
-// Lower-triangular 128-tile p; false when it holds no strict block-lower entry.
-__device__ __forceinline__ bool tile128_of(const Dense& P, int p, int& TJ, int& TI) {
-    tile_coords(p, TJ, TI);
+// False when the 128-tile (TJ, TI) holds no strict block-lower entry.
+__device__ __forceinline__ bool tile128_needed(const Dense& P, int TJ, int TI) {
     const int rlast = min(TJ * kBig + kBig - 1, P.sb - 1);
     return (TI * kBig) / P.b < rlast / P.b;
 }
 
+// Position L of the lower-triangular 128-tiles (NT per side) in an order
+// that takes them 8 x 8 at a time (super-tiles row by row, the diagonal
+// super-tile as a triangle): 64 consecutive tiles then read 16 row panels
+// instead of up to 65.
+__device__ __forceinline__ void grouped_tile128(int L, int NT, int& TJ, int& TI) {
+    constexpr int S = 8;
+    int acc = 0;
+    for (int SJ = 0; SJ * S < NT; ++SJ) {
+        const int rows = min(S, NT - SJ * S);
+        for (int SI = 0; SI <= SJ; ++SI) {
+            const int cnt = SI < SJ ? rows * S : rows * (rows + 1) / 2;
+            if (L < acc + cnt) {
+                const int l = L - acc;
+                if (SI < SJ) {
+                    TJ = SJ * S + l / S;
+                    TI = SI * S + l % S;
+                } else {
+                    tile_coords(l, TJ, TI);
+                    TJ += SJ * S;
+                    TI += SI * S;
+                }
+                return;
+            }
+            acc += cnt;
+        }
+    }
+    TJ = TI = 0;   // not reached for L < NT (NT + 1) / 2
+}
+
+template <int DT, bool GEN = true>
+__device__ __forceinline__ void gram_tile128_at(const Dense& P, float* Gout, uint64_t h, int TJ,
+                                                int TI, unsigned char* lds);
+
+// Lower-triangular 128-tile p in row order.
 template <int DT, bool GEN = true>
 __device__ __forceinline__ void gram_tile128(const Dense& P, float* Gout, uint64_t h, int tile,
                                              unsigned char* lds) {
-    using T = typename Store<DT>::T;
     int TJ, TI;
-    if (!tile128_of(P, tile, TJ, TI)) return;   // the same for the whole workgroup
+    tile_coords(tile, TJ, TI);
+    gram_tile128_at<DT, GEN>(P, Gout, h, TJ, TI, lds);
+}
+
+// acc = the products of the tile's row panels over K chunks [c0, c1) of
+// 128 bytes (c0 < c1). Lane l of wave w holds, in acc[a][b][v], row
+// TJ*128 + (w/2)*64 + 16a + 4(l/16) + v, column TI*128 + (w%2)*64 + 16b + l%16.
+template <int DT>
+__device__ __forceinline__ void gram128_acc(const Dense& P, uint64_t h, int TJ, int TI, int c0,
+                                            int c1, unsigned char* lds, v4f (&acc)[4][4]) {
+    using T = typename Store<DT>::T;
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wy = w >> 1, wx = w & 1;
-    const int slot = slot_of(h);
-    const unsigned char* Yb = static_cast<const unsigned char*>(pick3(P.Y, slot));
+    const unsigned char* Yb = static_cast<const unsigned char*>(pick3(P.Y, slot_of(h)));
     const int64_t ldb = P.ldy * (int64_t)sizeof(T);
-    const int nch = (int)((P.n * (int64_t)sizeof(T) + kChunkB - 1) / kChunkB);
     unsigned char* As = lds;
     unsigned char* Bs = lds + (size_t)kBig * kRowB;
     // global -> LDS assignment: 1024 16-byte pieces per panel and chunk,
@@ -454,21 +503,20 @@ __device__ __forceinline__ void gram_tile128(const Dense& P, float* Gout, uint64
         const int v = tid + 256 * i, row = v >> 3, seg = v & 7;
         ga[i] = Yb + (int64_t)(TJ * kBig + row) * ldb + seg * 16;
         gb[i] = Yb + (int64_t)(TI * kBig + row) * ldb + seg * 16;
-        lo[i] = row * kRowB + seg * 16;
+        lo[i] = row * kRowB + (seg ^ swz128(row)) * 16;
     }
     // two register sets: the loads of chunk c+2 are issued before the MFMAs
     // of chunk c (two chunks of MFMA work cover the L2 latency); every load
     // is unconditional (past the end it re-reads the last chunk, unused)
     u32x4 ra0[4], rb0[4], ra1[4], rb1[4];
     auto gload = [&](u32x4 (&ra)[4], u32x4 (&rb)[4], int c) {
-        const int64_t off = (int64_t)(c < nch ? c : nch - 1) * kChunkB;
+        const int64_t off = (int64_t)(c < c1 ? c : c1 - 1) * kChunkB;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             ra[i] = *reinterpret_cast<const u32x4*>(ga[i] + off);
             rb[i] = *reinterpret_cast<const u32x4*>(gb[i] + off);
         }
     };
-    v4f acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -481,10 +529,12 @@ __device__ __forceinline__ void gram_tile128(const Dense& P, float* Gout, uint64
             *reinterpret_cast<u32x4*>(Bs + lo[i]) = rb[i];
         }
     };
+    // every row this lane reads is (lane & 15) modulo 16: one swizzle
+    const int sw = swz128(lane & 15);
     auto compute = [&]() {
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
-            const int so = ((lane >> 4) + 4 * half) * 16;
+            const int so = (((lane >> 4) + 4 * half) ^ sw) * 16;
             V16 av[4], bv[4];
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
@@ -504,16 +554,16 @@ __device__ __forceinline__ void gram_tile128(const Dense& P, float* Gout, uint64
                     for (int b = 0; b < 4; ++b) mfma_q<DT>(av[a], bv[b], q, acc[a][b]);
         }
     };
-    gload(ra0, rb0, 0);
-    gload(ra1, rb1, 1);
+    gload(ra0, rb0, c0);
+    gload(ra1, rb1, c0 + 1);
 #pragma unroll 1
-    for (int c = 0; c < nch; c += 2) {
+    for (int c = c0; c < c1; c += 2) {
         stage(ra0, rb0);
         lds_barrier();
         gload(ra0, rb0, c + 2);
         compute();
         lds_barrier();
-        if (c + 1 < nch) {   // the same for the whole workgroup
+        if (c + 1 < c1) {   // the same for the whole workgroup
             stage(ra1, rb1);
             lds_barrier();
             gload(ra1, rb1, c + 3);
@@ -521,26 +571,142 @@ __device__ __forceinline__ void gram_tile128(const Dense& P, float* Gout, uint64
             lds_barrier();
         }
     }
+}
+
+// Entry (t, u) of the tile with value g: written when it is a strict
+// block-lower entry inside sb x sb, with the row scales applied.
+template <bool GEN>
+__device__ __forceinline__ void gram128_put(const Dense& P, float* Gout, const float* sI, int t,
+                                            int u, float g) {
+    if (t < P.sb && u < P.sb && u / P.b < t / P.b) {
+        const float sr = P.scale ? sI[t] : 1.0f;
+        const float sc = P.scale ? sI[u] : 1.0f;
+        Gout[(int64_t)t * P.ldg + u] = e2e_round(g * sr * sc, e2e_mode<GEN>(P));
+    }
+}
+
+template <int DT, bool GEN>
+__device__ __forceinline__ void gram_tile128_at(const Dense& P, float* Gout, uint64_t h, int TJ,
+                                                int TI, unsigned char* lds) {
+    using T = typename Store<DT>::T;
+    if (!tile128_needed(P, TJ, TI)) return;   // the same for the whole workgroup
+    const int nch = (int)((P.n * (int64_t)sizeof(T) + kChunkB - 1) / kChunkB);
+    v4f acc[4][4];
+    gram128_acc<DT>(P, h, TJ, TI, 0, nch, lds, acc);
     // store: lane l, register v hold row 4 (l / 16) + v, column l % 16 of a
-    // 16 x 16 tile; strict block-lower entries inside sb x sb only
-    const float* sI = pick3(P.sI, slot);
-    const int li = lane & 15, lg = lane >> 4;
+    // 16 x 16 tile
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wy = w >> 1, wx = w & 1, li = lane & 15, lg = lane >> 4;
+    const float* sI = pick3(P.sI, slot_of(h));
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const int u = TI * kBig + wx * 64 + 16 * b + li;
-        const float sc = (P.scale && u < P.sb) ? sI[u] : 1.0f;
-        const int bu = u / P.b;
+    for (int b = 0; b < 4; ++b)
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int t = TJ * kBig + wy * 64 + 16 * a + 4 * lg + v;
-                if (t < P.sb && u < P.sb && bu < t / P.b) {
-                    const float sr = P.scale ? sI[t] : 1.0f;
-                    Gout[(int64_t)t * P.ldg + u] =
-                        e2e_round(acc[a][b][v] * sr * sc, e2e_mode<GEN>(P));
+            for (int v = 0; v < 4; ++v)
+                gram128_put<GEN>(P, Gout, sI, TJ * kBig + wy * 64 + 16 * a + 4 * lg + v,
+                                 TI * kBig + wx * 64 + 16 * b + li, acc[a][b][v]);
+}
+
+// ------------------------------------ Gram, 128 x 128 tiles split along K
+// For Gram matrices with fewer 128-tiles than the device holds workgroups,
+// each tile is split into S pieces of consecutive K chunks, one workgroup
+// each (all resident: a cooperative launch). Every piece writes its 128 x 128
+// partial sums as tagged 64-bit words (value bits low, the launch's tag high,
+// single-copy-atomic relaxed accesses: no fence or cache write-back), then
+// reduces 1/S of the tile's entries: for each it waits for the S partials
+// and adds them in piece order, so the result does not depend on timing.
+// Slot q of a tile holds word k * 256 + tid for value k (0..63) of thread
+// tid of piece q.
+constexpr int kGramSkWords = kBig * kBig;   // 64-bit words per partial
+
+__device__ __forceinline__ void sk_put(unsigned long long* p, unsigned tag, float v) {
+    __hip_atomic_store(p, ((unsigned long long)tag << 32) | __float_as_uint(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bounded wait for the tagged value at p; false (timeout flag raised, or
+// another workgroup timed out) when it does not arrive.
+__device__ __forceinline__ bool sk_wait(const unsigned long long* p, unsigned tag, float& v,
+                                        unsigned* flags, unsigned long long spin) {
+    unsigned long long n = 0;
+    for (;;) {
+        const unsigned long long x = __hip_atomic_load(const_cast<unsigned long long*>(p),
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((unsigned)(x >> 32) == tag) {
+            v = __uint_as_float((unsigned)x);
+            return true;
+        }
+        if (++n > spin) {
+            raise_flag(flags, FLAG_TIMEOUT);
+            return false;
+        }
+        if ((n & 63ull) == 0 && atomic_load_relaxed(flags + FLAG_TIMEOUT)) return false;
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// Piece p of S (1 < S <= 16, S <= the tile's K chunks) of tile (TJ, TI);
+// `slots` = the tile's S partial slots.
+template <int DT, bool GEN = true>
+__device__ __forceinline__ void gram_tile128_piece(const Dense& P, float* Gout, uint64_t h, int TJ,
+                                                   int TI, int p, int S, unsigned long long* slots,
+                                                   unsigned tag, unsigned long long spin,
+                                                   unsigned char* lds) {
+    using T = typename Store<DT>::T;
+    if (!tile128_needed(P, TJ, TI)) return;   // the same for all pieces
+    const int nch = (int)((P.n * (int64_t)sizeof(T) + kChunkB - 1) / kChunkB);
+    const int c0 = (int)((int64_t)p * nch / S), c1 = (int)((int64_t)(p + 1) * nch / S);
+    v4f acc[4][4];
+    gram128_acc<DT>(P, h, TJ, TI, c0, c1, lds, acc);
+    const int tid = threadIdx.x;
+    unsigned long long* mine = slots + (size_t)p * kGramSkWords + tid;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sk_put(mine + ((a * 4 + b) * 4 + v) * 256, tag, acc[a][b][v]);
+    // this piece's share of the entries: values k0 .. k1-1 of every thread
+    const int lane = tid & 63, w = tid >> 6;
+    const int wy = w >> 1, wx = w & 1, li = lane & 15, lg = lane >> 4;
+    const float* sI = pick3(P.sI, slot_of(h));
+    const int k0 = p * 64 / S, k1 = (p + 1) * 64 / S;
+    // rounds of KB values: the KB * S words of a round are loaded at once
+    // (up to 16 in flight), then checked; a word not there yet is polled
+    const int KB = 16 / S;
+    bool ok = true;
+    for (int kb = k0; kb < k1 && ok; kb += KB) {
+        unsigned long long wv[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int kk = i / S, q = i - kk * S;
+            if (kk < KB && kb + kk < k1)
+                wv[i] = __hip_atomic_load(slots + (size_t)q * kGramSkWords + (kb + kk) * 256 + tid,
+                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        float g = 0.f;   // piece sums of one value, added in piece order
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int kk = i / S, q = i - kk * S, k = kb + kk;
+            if (ok && kk < KB && k < k1) {
+                float v;
+                if ((unsigned)(wv[i] >> 32) == tag) {
+                    v = __uint_as_float((unsigned)wv[i]);
+                } else if (!sk_wait(slots + (size_t)q * kGramSkWords + k * 256 + tid, tag, v,
+                                    P.flags, spin)) {
+                    ok = false;
+                    continue;
+                }
+                g += v;
+                if (q == S - 1) {
+                    const int a = k >> 4, b = (k >> 2) & 3, r = k & 3;
+                    gram128_put<GEN>(P, Gout, sI, TJ * kBig + wy * 64 + 16 * a + 4 * lg + r,
+                                     TI * kBig + wx * 64 + 16 * b + li, g);
+                    g = 0.f;
                 }
             }
+        }
     }
 }
 

@@ -27,13 +27,16 @@ int slice_width_of(int dtype);     // columns per update / margin slice
 // Workspace layout of one dense problem (byte offsets, 256-byte aligned).
 struct DenseLayout {
     int sb, ts, ntiles, needed, gt, bt, gna, ksplit, nslices, t128, n128;
+    int sk_nslots;      // partial slots of the stand-alone K-split Gram region (0: none)
     int64_t kchunk, ldy, ldg;
     size_t off_flags, off_tilecnt, off_G0, off_G1, off_Gpart, off_rp0, off_rp1, off_c, off_r, off_pub,
         off_Y[3], off_yI[3], off_sI[3], total;
+    size_t total_sk;    // total plus the K-split Gram region (epoch line + slots)
 };
 
 bool dense_layout(int64_t n, int dtype, int b, int s, DenseLayout* L);
-void dense_bind(const DenseLayout& L, void* ws, Dense* P);
+// Binds the workspace; the K-split Gram region is used when ws_bytes holds it.
+void dense_bind(const DenseLayout& L, void* ws, size_t ws_bytes, Dense* P);
 
 // Tuning knobs chosen by the host (or the autotuner).
 struct FitPlan {

@@ -131,6 +131,66 @@ def test_gram_margin_vs_oracle(cg, fmt, case, gram_tile):
         assert np.all(np.abs(r - parts["r"]) <= rb)
 
 
+@pytest.mark.parametrize("fmt", ["f32", "bf16", "fp8"])
+@pytest.mark.parametrize("n,b,s", [(8200, 32, 8), (8192, 64, 2), (9000, 16, 24)])
+def test_gram_ksplit_vs_oracle(cg, fmt, n, b, s):
+    """128 x 128 tiles split along K (few tiles, long K; ragged K tail): every
+    strict block-lower entry within the Gram bound of the oracle's, two launches
+    on one workspace bitwise equal (each tags its exchange words with a new
+    epoch), and equal to rounding to the unsplit tiles."""
+    m = 3000
+    p = dense_logreg(m, n, 11, var=1.0 / n, noise_var=0.1, dtype=np.float32)
+    code = {"f32": cg.F32, "bf16": cg.BF16, "fp8": cg.FP8E4M3}[fmt]
+    dst, sc = cg.casgd_quantize(_to_dev(p.X), code)
+    X = cg.dense_matrix(dst, sc, n=n)
+    _, _, exact = R.quantize(p.X, fmt)
+    big = cg.casgd_gram_workspace_size(X, b, s)
+    assert big > cg.casgd_workspace_size(X, b, s)   # this shape is split
+    ws = cg.workspace(big)
+    o = cg.opts(gram_tile=128)
+    mask = R.strict_block_lower_mask(b, s)
+    for h in (0, 5):
+        G1, _ = cg.casgd_gram_margin(X, None, b, s, 42, h, ws=ws, opts=o)
+        G2, _ = cg.casgd_gram_margin(X, None, b, s, 42, h, ws=ws, opts=o)
+        G0, _ = cg.casgd_gram_margin(X, None, b, s, 42, h, opts=o,
+                                     ws=cg.workspace(cg.casgd_workspace_size(X, b, s)))
+        cg.casgd_check(ws)
+        G1 = G1.cpu().numpy().astype(np.float64)
+        assert np.array_equal(G1, G2.cpu().numpy().astype(np.float64))
+        parts = R.outer_parts(exact, p.y, np.zeros(n), 0.5, 0.0, b, s, 42, h)
+        Y = exact[parts["idx"]]
+        bound = 2 * R.gamma(n + 2, U32) * (np.abs(Y) @ np.abs(Y).T) + 1e-30
+        err = np.abs(G1 - parts["G"])
+        assert np.all(err[mask] <= bound[mask]), (h, float((err / bound)[mask].max()))
+        G0 = G0.cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(G1 - G0)[mask] <= 2 * bound[mask])
+
+
+def test_gram_ksplit_remainder_vs_oracle(cg):
+    """More 128-tiles than the device holds workgroups (s*b = 4096: 528 tiles):
+    whole rounds of tiles, then the remaining tiles split along K. Sampled
+    rows of G against the oracle within the Gram bound."""
+    m, n, b, s = 8192, 4096, 32, 128
+    p = dense_logreg(m, n, 12, var=1.0 / n, noise_var=0.1, dtype=np.float32)
+    dst, sc = cg.casgd_quantize(_to_dev(p.X), cg.BF16)
+    X = cg.dense_matrix(dst, sc, n=n)
+    _, _, exact = R.quantize(p.X, "bf16")
+    big = cg.casgd_gram_workspace_size(X, b, s)
+    assert big > cg.casgd_workspace_size(X, b, s)
+    ws = cg.workspace(big)
+    G, _ = cg.casgd_gram_margin(X, None, b, s, 42, 1, ws=ws, opts=cg.opts(gram_tile=128))
+    cg.casgd_check(ws)
+    G = G.cpu().numpy().astype(np.float64)
+    idx = R.sample_indices(42, 1 * s * b, s * b, m)
+    Y = exact[idx]
+    rows = np.r_[np.arange(3968, 4096), np.random.default_rng(3).choice(4096, 256, replace=False)]
+    mask = R.strict_block_lower_mask(b, s)[rows]
+    ref = Y[rows] @ Y.T
+    bound = 2 * R.gamma(n + 2, U32) * (np.abs(Y[rows]) @ np.abs(Y).T) + 1e-30
+    err = np.abs(G[rows] - ref)
+    assert np.all(err[mask] <= bound[mask]), float((err / bound)[mask].max())
+
+
 # ---------------------------------------------------------------- recurrence
 
 @pytest.mark.parametrize("b,s", [(16, 4), (32, 8), (64, 16), (24, 5), (128, 8), (3, 11)])
