@@ -699,6 +699,9 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=list(DT_NAME))
     ap.add_argument("--exec-mode", type=int, default=0, help="0 automatic, 1 fused, 2 stream")
     ap.add_argument("--variant", type=int, default=0)
+    ap.add_argument("--grid", type=int, default=0, help="workgroups of the fused launch (0 = auto)")
+    ap.add_argument("--grid-sweep", action="store_true",
+                    help="time the fused launch at --s over grid sizes 8 .. 256")
     ap.add_argument("--m", type=int, default=1 << 20)
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--sweep", action="store_true")
@@ -782,6 +785,8 @@ def main():
     K = args.steps if args.steps is not None else max(8, (1 << 16) // s)
     W = args.warmup if args.warmup is not None else K
     okw = dict(exec_mode=args.exec_mode, fused_variant=args.variant)
+    if args.grid > 0:
+        okw["grid_blocks"] = args.grid
     ms, x, ws = timed_fit(cg, X, y, n, b, s, ETA_C2, LAMBDA_C2, K, W, okw)
     ups = s * K / (ms * 1e-3)
     log(f"[bench] s={s} {dtype}: {K} outer in {ms:.2f} ms -> {ups:,.0f} updates/s")
@@ -818,6 +823,16 @@ def main():
     }
     if not args.no_gram and s > 1:
         out["roofline_gram"] = gram_roofline(cg, X, n, b, s, dtype)
+    if args.grid_sweep:
+        rows = []
+        for g in (8, 16, 32, 64, 128, 256):
+            Kg = max(8, (1 << 15) // s)
+            msg, _, _ = timed_fit(cg, X, y, n, b, s, ETA_C2, LAMBDA_C2, Kg, max(2, Kg // 20),
+                                  dict(okw, grid_blocks=g))
+            rows.append({"s": s, "grid": g, "us_per_outer": round(msg * 1e3 / Kg, 2),
+                         "updates_per_s": round(s * Kg / (msg * 1e-3), 1)})
+            log(f"[grid] s={s} grid={g}: {rows[-1]}")
+        out["grid_sweep"] = rows
     if args.sweep:
         rows = []
         for ss in (1, 4, 16, 32):

@@ -125,8 +125,31 @@ def best_eta(X, y, Xt, yt, n, lam, b, s, seed, n_outer, grid=None):
     return best[1]
 
 
+def best_eta_plateau(X, y, Xt, yt, n, lam, b, s, seed, n_outer, grid, snaps: int = 16):
+    """Step size of `grid` with the lowest mean held-out loss over the second
+    half of an n_outer run (snapshots every n_outer / snaps outer iterations):
+    constant-step SGD ends on a plateau whose height grows with the step, and
+    a short run alone would favour steps that settle too high."""
+    every = max(1, n_outer // snaps)
+    best = None
+    for eta in grid:
+        try:
+            losses = loss_curve(X, y, Xt, yt, n, eta, lam, b, s, seed, every * snaps, every)
+        except cg.CasgdError:       # diverged (non-finite iterate)
+            continue
+        tail = np.asarray(losses[len(losses) // 2:], dtype=np.float64)
+        if tail.size and np.all(np.isfinite(tail)):
+            score = float(tail.mean())
+            if best is None or score < best[0]:
+                best = (score, eta)
+    return best[1]
+
+
 def targets(dp: DeviceProblem, lam: float, b: int, s: int, seed: int, epochs: float = 2.0):
-    """(t_d per column, log (eta r2) for the rescaled problem, plain best eta)."""
+    """(t_d per column, log (eta r2) for the rescaled problem, plain best eta).
+    The plain step is the best of a short sweep (it only has to give a usable
+    solution for the Hessian); the rescaled problem's step is the best for the
+    plateau of an `epochs` run."""
     X = stored(dp)
     n_outer = max(2, int(epochs * dp.m / (b * s)))
     short = max(2, n_outer // 4)
@@ -136,8 +159,8 @@ def targets(dp: DeviceProblem, lam: float, b: int, s: int, seed: int, epochs: fl
     t_d, q = cg.casgd_jacobi_target(h)
     Xq = stored(dp, q)
     r2 = mean_row_norm2(Xq)
-    eta1 = best_eta(Xq, dp.y, stored_test(dp, q), dp.yt, dp.n, lam, b, s, seed, short,
-                    grid=[2.0 ** k / r2 for k in ETA_K])
+    eta1 = best_eta_plateau(Xq, dp.y, stored_test(dp, q), dp.yt, dp.n, lam, b, s, seed, n_outer,
+                            grid=[2.0 ** k / r2 for k in ETA_K])
     return t_d, math.log(eta1 * r2), eta0
 
 
