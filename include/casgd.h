@@ -360,10 +360,10 @@ casgd_status casgd_gram_workspace_size(const casgd_matrix *X, int32_t b, int32_t
 /* casgd_gram_workspace_size: workspace bytes of casgd_gram_margin (and of
  * stream-ordered fits, exec_mode 2) that include the exchange region of the
  * K-split Gram: casgd_workspace_size plus, when the split applies to this
- * shape, an epoch word and one 128 x 128 slot of 64-bit words per piece. The
- * region must be zero when the workspace is first used (a zero-filled
- * allocation) and is never cleared by the library: each launch tags its words
- * with a new epoch. Dense X only. */
+ * shape, an epoch line and one 128 x 128 slot of 64-bit words per piece. Each
+ * launch tags its words with a new epoch; the library clears the region when
+ * its marker word is not set (first use, or a workspace that held other data),
+ * which costs one extra pass over it. Dense X only. */
 casgd_status casgd_gram_margin(const casgd_matrix *X, const float *x, int32_t b,
                                int32_t s, uint64_t seed, uint64_t outer_iter, float *G,
                                float *r, const casgd_opts *opts, void *ws, size_t ws_bytes,

@@ -272,8 +272,8 @@ def casgd_gram_workspace_size(X: MatrixRef, b: int, s: int) -> int:
 
 def casgd_gram_margin(X: MatrixRef, x, b: int, s: int, seed: int, outer_iter: int, G=None,
                       r=None, ws=None, stream=None, opts=None):
-    """Margins and Gram of one outer iteration. The workspace (zero-filled when
-    allocated here) holds the K-split Gram's exchange region."""
+    """Margins and Gram of one outer iteration. The workspace (allocated here
+    when None) holds the K-split Gram's exchange region."""
     torch = _torch()
     sb = s * b
     G = G if G is not None else torch.zeros(sb, sb, dtype=torch.float32, device="cuda")

@@ -10,7 +10,9 @@ updates per second over the launch choices the library exposes:
     build the next Gram matrix; variant 3: the chain and helper workgroups
     run it while the others build the next Gram matrix) or the
     stream-ordered kernel sequence,
-  * the fused launch's grid size.
+  * the fused launch's grid size,
+  * the Gram work unit (64-row units whose waves split K, or 128 x 128
+    LDS-staged tiles) for s > 1.
 
 Candidates a shape does not support (variant 3 needs b in {16, 32, 64, 128}
 and s > 1) are skipped. Results persist in a JSON table keyed by (dtype, b,
@@ -38,6 +40,7 @@ class Choice:
     variant: int
     grid_blocks: int
     updates_per_s: float
+    gram_tile: int = 0    # 0 automatic, 64 or 128
 
 
 def _bucket(v: int) -> int:
@@ -70,30 +73,34 @@ def _time_fit(X, y, b, s, eta, lam, seed, o, budget_s: float) -> float:
 
 
 def tune(X, y, b: int, eta: float = 0.5, lam: float = 1e-5, seed: int = 0,
-         s_grid=S_GRID, modes=MODES, grids=(0,), budget_s: float = 0.02,
+         s_grid=S_GRID, modes=MODES, grids=(0,), tiles=(64, 128), budget_s: float = 0.02,
          verbose: bool = False, results: list | None = None) -> Choice:
     """Measure every candidate on (X, y) and return the fastest (every
-    measured candidate is appended to `results` when given)."""
+    measured candidate is appended to `results` when given). `tiles`: Gram
+    unit kinds tried for s > 1."""
     best = None
     for s in s_grid:
         if s * b > 4096:
             continue
         for em, var in modes:
             for gb in (grids if em == 0 else (0,)):
-                o = cg.opts(exec_mode=em, fused_variant=var, grid_blocks=gb)
-                try:
-                    t = _time_fit(X, y, b, s, eta, lam, seed, o, budget_s)
-                except cg.CasgdError as e:
+                for gt in (tiles if s > 1 else (0,)):
+                    o = cg.opts(exec_mode=em, fused_variant=var, grid_blocks=gb, gram_tile=gt)
+                    what = f"s={s} mode={em}/{var} grid={gb} tile={gt}"
+                    try:
+                        t = _time_fit(X, y, b, s, eta, lam, seed, o, budget_s)
+                    except cg.CasgdError as e:
+                        if verbose:
+                            print(f"{what}: {e}")
+                        continue
+                    ups = s / t   # SGD updates (mini-batches) per second
+                    c = Choice(s, em, var, gb, ups, gt)
+                    if results is not None:
+                        results.append(c)
                     if verbose:
-                        print(f"s={s} mode={em}/{var} grid={gb}: {e}")
-                    continue
-                ups = s / t   # SGD updates (mini-batches) per second
-                if results is not None:
-                    results.append(Choice(s, em, var, gb, ups))
-                if verbose:
-                    print(f"s={s} mode={em}/{var} grid={gb}: {ups:.0f} updates/s")
-                if best is None or ups > best.updates_per_s:
-                    best = Choice(s, em, var, gb, ups)
+                        print(f"{what}: {ups:.0f} updates/s")
+                    if best is None or ups > best.updates_per_s:
+                        best = c
     if best is None:
         raise RuntimeError("no candidate ran")
     return best
@@ -130,4 +137,4 @@ class Table:
 
     def opts(self, c: Choice, **kw):
         return cg.opts(exec_mode=c.exec_mode, fused_variant=c.variant,
-                       grid_blocks=c.grid_blocks, **kw)
+                       grid_blocks=c.grid_blocks, gram_tile=c.gram_tile, **kw)

@@ -87,7 +87,23 @@ __global__ __launch_bounds__(kNT) void k_gram128_sk(Dense P, float* Gout, uint64
 }
 
 // Next launch tag of the K-split Gram (never 0, the tag of a cleared word).
-__global__ void k_sk_epoch(unsigned* e) {
+// The region is cleared first when its marker word is not set: on first use,
+// or when a workspace that held other data (another shape's layout) is
+// reused, so a stale word can never carry a future tag. One workgroup.
+constexpr unsigned kSkMagic = 0x6b53706cu;
+
+__global__ __launch_bounds__(1024) void k_sk_epoch(unsigned* e, unsigned long long* slots,
+                                                   int64_t nwords) {
+    __shared__ int fresh;
+    if (threadIdx.x == 0) fresh = e[1] != kSkMagic;
+    __syncthreads();
+    if (fresh) {
+        for (int64_t i = threadIdx.x; i < nwords; i += blockDim.x) slots[i] = 0ull;
+        if (threadIdx.x == 0) {
+            e[0] = 0u;
+            e[1] = kSkMagic;
+        }
+    }
     if (threadIdx.x == 0) {
         const unsigned v = e[0] + 1u;
         e[0] = v ? v : 1u;
@@ -162,7 +178,8 @@ casgd_status launch_gram_t(const Dense& P, float* Gout, uint64_t h, hipStream_t 
         const int nch = (int)((P.n * (int64_t)sizeof(T) + kChunkB - 1) / kChunkB);
         const int S = rem > 0 ? std::min({16, nch / 16, R / rem, P.sk_nslots / rem}) : 0;
         if (S >= 2) {
-            hipLaunchKernelGGL(k_sk_epoch, dim3(1), dim3(64), 0, st, P.sk_epoch);
+            hipLaunchKernelGGL(k_sk_epoch, dim3(1), dim3(1024), 0, st, P.sk_epoch, P.sk_slots,
+                               (int64_t)P.sk_nslots * kGramSkWords);
             CASGD_HIP(hipGetLastError());
             Dense Pc = P;
             int Tw = Tn - rem, Sv = S;

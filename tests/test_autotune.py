@@ -21,8 +21,11 @@ def test_table_round_trip(tmp_path):
     t.save()
     t2 = at.Table(str(p))
     c = t2.get(6000, 250, 1, 64)
-    assert c is not None and c.s == 16 and c.variant == 1
+    assert c is not None and c.s == 16 and c.variant == 1 and c.gram_tile == 0
     assert t2.get(6000, 250, 1, 32) is None
+    t2.entries[at.key(5000, 200, 1, 32)] = dict(s=8, exec_mode=0, variant=3, grid_blocks=0,
+                                                updates_per_s=2e4, gram_tile=128)
+    assert t2.get(5000, 200, 1, 32).gram_tile == 128
     assert json.loads(p.read_text())
 
 
@@ -37,6 +40,8 @@ def test_tune_small_problem(tmp_path):
     y = torch.from_numpy(np.where(g.random(8192) < 0.5, -1.0, 1.0).astype(np.float32)).cuda()
     Xm = cg.dense_matrix(X)
     t = at.Table(str(tmp_path / "t.json"))
-    c = t.lookup_or_tune(Xm, y, 32, s_grid=(1, 4, 16), budget_s=0.003)
+    res = []
+    c = t.lookup_or_tune(Xm, y, 32, s_grid=(1, 4, 16), budget_s=0.003, results=res)
     assert c.s in (1, 4, 16) and c.updates_per_s > 0
+    assert {r.gram_tile for r in res if r.s > 1} == {64, 128}
     assert t.get(8192, 256, cg.F32, 32) == c

@@ -146,7 +146,9 @@ def test_gram_ksplit_vs_oracle(cg, fmt, n, b, s):
     _, _, exact = R.quantize(p.X, fmt)
     big = cg.casgd_gram_workspace_size(X, b, s)
     assert big > cg.casgd_workspace_size(X, b, s)   # this shape is split
-    ws = cg.workspace(big)
+    # a workspace full of other data: the exchange region is cleared on first use
+    ws = torch.full((big,), 0x55, dtype=torch.uint8, device="cuda")
+    cg.casgd_reset(ws)   # the flag words
     o = cg.opts(gram_tile=128)
     mask = R.strict_block_lower_mask(b, s)
     for h in (0, 5):
