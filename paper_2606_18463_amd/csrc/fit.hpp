@@ -258,10 +258,16 @@ __global__ __launch_bounds__(kNT) void k_fit_batch(const Dense* table, const int
         fit_body<DT, float, true, GEN>(P, wg, P.gsize, spin, lds);
 }
 
+// The problem is read in place from the kernel-argument segment (scalar
+// loads through the constant cache, as the batched kernel reads its table):
+// bound to a reference, the by-value parameter was copied into per-lane
+// scratch memory (432 bytes) and every field access became a vector load.
 template <int DT, typename ACC, bool GEN>
 __global__ __launch_bounds__(kNT) void k_fit(Dense P, unsigned long long spin) {
     extern __shared__ __align__(16) unsigned char lds[];
-    fit_body<DT, ACC, true, GEN>(P, blockIdx.x, gridDim.x, spin, lds);
+    (void)P;   // the first kernel argument: at offset 0 of the segment
+    const Dense& Pk = *(const Dense*)__builtin_amdgcn_kernarg_segment_ptr();
+    fit_body<DT, ACC, true, GEN>(Pk, blockIdx.x, gridDim.x, spin, lds);
 }
 
 

@@ -57,9 +57,14 @@ __host__ __device__ inline size_t sparse_lds_bytes(int sb, int s, int acc_bytes,
 //   P3  margins(h+1), clear buckets(h)
 //   --  barrier
 template <typename ACC>
-__global__ __launch_bounds__(kNT) void k_sparse_fit(Sparse S, uint64_t h0, int64_t H,
+__global__ __launch_bounds__(kNT) void k_sparse_fit(Sparse S_arg, uint64_t h0, int64_t H,
                                                     unsigned long long spin, int K, int R) {
     extern __shared__ __align__(16) unsigned char lds[];
+    // The problem is read in place from the kernel-argument segment (scalar
+    // loads through the constant cache): bound to references, the by-value
+    // parameter was copied into per-lane scratch memory (856 bytes).
+    (void)S_arg;   // the first kernel argument: at offset 0 of the segment
+    const Sparse& S = *(const Sparse*)__builtin_amdgcn_kernarg_segment_ptr();
     constexpr int NL = kLanesPerRecWG;
     ACC* dl = reinterpret_cast<ACC*>(lds);
     ACC* pw = dl + (size_t)S.sb * NL;
