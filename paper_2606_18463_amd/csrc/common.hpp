@@ -252,8 +252,14 @@ enum : int {
     FLAG_BAR_SUB = 352,   // a barrier among a subset of the workgroups
     FLAG_SLICES = 672,    // update slices finished in this launch (own line)
     FLAG_GRAM_CLAIM = 704,// Gram units claimed in this outer iteration, per parity (own line)
-    FLAG_WORDS = 736
+    FLAG_XCD_CENSUS = 736,// workgroups of the fused launch on each XCD (8 words, own line)
+    FLAG_WORDS = 768
 };
+
+// The XCD this workgroup runs on (hardware register XCC_ID, bits 3:0).
+__device__ __forceinline__ unsigned xcd_id() {
+    return (unsigned)__builtin_amdgcn_s_getreg(20 | (3 << 11)) & 7u;
+}
 
 // Entry points without a workspace pass flags == nullptr and report nothing.
 __device__ __forceinline__ void raise_flag(unsigned* flags, int which) {
@@ -355,6 +361,84 @@ __device__ __forceinline__ bool wait_count(unsigned* flags, int w, unsigned want
 __device__ __forceinline__ bool grid_barrier(unsigned* flags, unsigned member, unsigned nblocks,
                                              unsigned long long spin_limit) {
     return barrier_at(flags, FLAG_BAR_MAIN, member, nblocks, spin_limit);
+}
+
+// Arrival grouped by XCD for a launch whose XCD census is known (xcd_census):
+// each wave first waits for its own memory operations, so the workgroup's
+// stores have reached its XCD's L2 (the vector L1 is write-through); members
+// arrive with a relaxed count, and only the last arrival of each XCD writes
+// that L2 back (one agent-scope release per XCD instead of one per
+// workgroup, for the stores of every workgroup there). The exit keeps one
+// acquire per workgroup. `members`: workgroups of this barrier on this XCD;
+// `ngroups`: XCDs that hold any. Same words and bounded wait as barrier_at.
+__device__ __forceinline__ bool grid_barrier_xcd(unsigned* flags, unsigned members,
+                                                 unsigned ngroups,
+                                                 unsigned long long spin_limit) {
+    __shared__ int s_stop;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned* gen = flags + FLAG_BAR_MAIN + BAR_GEN;
+        unsigned* top = flags + FLAG_BAR_MAIN + BAR_TOP;
+        unsigned* cnt = flags + FLAG_BAR_MAIN + BAR_GROUP + 32 * xcd_id();
+        const unsigned g0 = atomic_load_relaxed(gen);
+        int stop = 0;
+        bool advanced = false;
+        const unsigned a = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (a == members - 1) {
+            fence_release_agent();
+            atomic_store_relaxed(cnt, 0u);
+            const unsigned t =
+                __hip_atomic_fetch_add(top, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (t == ngroups - 1) {
+                atomic_store_relaxed(top, 0u);
+                atomic_store_release(gen, g0 + 1u);
+                advanced = true;
+            }
+        }
+        if (!advanced) {
+            unsigned long long spins = 0;
+            while (atomic_load_relaxed(gen) == g0) {
+                if (++spins > spin_limit) {
+                    raise_flag(flags, FLAG_TIMEOUT);
+                    stop = 1;
+                    break;
+                }
+                if ((spins & 255ull) == 0 && atomic_load_relaxed(flags + FLAG_TIMEOUT)) {
+                    stop = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            fence_acquire_agent();
+        }
+        if (atomic_load_relaxed(flags + FLAG_TIMEOUT)) stop = 1;
+        s_stop = stop;
+    }
+    __syncthreads();
+    return s_stop == 0;
+}
+
+// Counts this workgroup in the launch's XCD census (before the launch's
+// first grid barrier; the census words start at zero).
+__device__ __forceinline__ void xcd_census_add(unsigned* flags) {
+    if (threadIdx.x == 0)
+        __hip_atomic_fetch_add(flags + FLAG_XCD_CENSUS + xcd_id(), 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// After the first grid barrier: workgroups on this XCD and XCDs in use.
+__device__ __forceinline__ void xcd_census_read(unsigned* flags, unsigned& members,
+                                                unsigned& ngroups) {
+    const unsigned me = xcd_id();
+    members = 0;
+    ngroups = 0;
+#pragma unroll
+    for (unsigned x = 0; x < 8; ++x) {
+        const unsigned c = atomic_load_relaxed(flags + FLAG_XCD_CENSUS + x);
+        if (c) ++ngroups;
+        if (x == me) members = c;
+    }
 }
 
 }  // namespace casgd

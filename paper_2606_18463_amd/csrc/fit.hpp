@@ -114,13 +114,18 @@ __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigne
 
     // Prologue: gather the rows of h0 and h0+1; then the Gram of h0 and the
     // margins of h0 from the incoming x.
+    // The first barrier also completes the XCD census; every later one
+    // writes each XCD's L2 back once (grid_barrier_xcd).
+    xcd_census_add(P.flags);
     gather_rows<DT>(P, h0, gw, ngw);
     if (H > 1) gather_rows<DT>(P, h0 + 1, gw, ngw);
     if (!grid_barrier(P.flags, wg, nb, spin)) return;
+    unsigned xm, xg;
+    xcd_census_read(P.flags, xm, xg);
     if (has_gram) gram_phase<DT, GEN>(P, P.G[0], h0, base, base + nb, lds);
     for (int sl = wg; sl < P.nslices; sl += nb)
         update_margin_slice<DT, kNW, GEN>(P, sl, nullptr, 0, false, h0, true, P.rp[0], red, xs, -1);
-    if (!grid_barrier(P.flags, wg, nb, spin)) return;
+    if (!grid_barrier_xcd(P.flags, xm, xg, spin)) return;
     for (int64_t hh = 0; hh < H; ++hh) {
         const uint64_t h = h0 + (uint64_t)hh;
         const int cur = (int)(hh & 1), nxt = cur ^ 1;
@@ -159,7 +164,7 @@ __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigne
                 gram_claim<DT, GEN>(P, pick2(P.G, nxt), h + 1, P.flags + FLAG_GRAM_CLAIM + (hh & 1), lds);
             if (wg == nrec) phase_mark(P, hh, 2);
             if (wg == nb - 1) phase_mark(P, hh, 6);
-            if (!grid_barrier(P.flags, wg, nb, spin)) return;
+            if (!grid_barrier_xcd(P.flags, xm, xg, spin)) return;
             if (wg == 0) phase_mark(P, hh, 3);
             // every claim of this outer iteration is done: reset the counter of
             // this parity, next used two outer iterations on
@@ -199,7 +204,7 @@ __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigne
                                (wg - P.nslices) * kNT + (int)threadIdx.x, (nb - P.nslices) * kNT);
             }
             if (wg == nb - 1) phase_mark(P, hh, 7);
-            if (!grid_barrier(P.flags, wg, nb, spin)) return;
+            if (!grid_barrier_xcd(P.flags, xm, xg, spin)) return;
             if (wg == 0) phase_mark(P, hh, 5);
             if (!split && more) {
                 if (wg < nrec) {
@@ -218,7 +223,7 @@ __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigne
             }
             if (has_gram && more) gram_phase<DT, GEN>(P, pick2(P.G, nxt), h + 1, base, base + nb, lds);
             if (more2) gather_rows<DT>(P, h + 2, gw, ngw);
-            if (!grid_barrier(P.flags, wg, nb, spin)) return;
+            if (!grid_barrier_xcd(P.flags, xm, xg, spin)) return;
         } else {
             if (wg == 0) {
                 recurrence<ACC, kNT, GEN>(P, pick2(P.G, cur), pick2(P.rp, cur), h, nullptr, nullptr, P.c,
@@ -229,11 +234,11 @@ __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigne
                     gram_phase<DT, GEN>(P, pick2(P.G, nxt), h + 1, base + 1, base + nb, lds);
                 if (more2) gather_rows<DT>(P, h + 2, gw1, ngw1);
             }
-            if (!grid_barrier(P.flags, wg, nb, spin)) return;
+            if (!grid_barrier_xcd(P.flags, xm, xg, spin)) return;
             for (int sl = wg; sl < P.nslices; sl += nb)
                 update_margin_slice<DT, kNW, GEN>(P, sl, P.c, h, true, h + 1, more, pick2(P.rp, nxt), red,
                                              xs, snap_row);
-            if (!grid_barrier(P.flags, wg, nb, spin)) return;
+            if (!grid_barrier_xcd(P.flags, xm, xg, spin)) return;
         }
         if (snap && wg == 0 && threadIdx.x == 0 && P.t_hist)
             P.t_hist[snap_row + 1] = (int64_t)wall_clock64();
