@@ -253,7 +253,9 @@ enum : int {
     FLAG_SLICES = 672,    // update slices finished in this launch (own line)
     FLAG_GRAM_CLAIM = 704,// Gram units claimed in this outer iteration, per parity (own line)
     FLAG_XCD_CENSUS = 736,// workgroups of the fused launch on each XCD (8 words, own line)
-    FLAG_WORDS = 768
+    FLAG_SLICE_CENSUS = 768, // update-slice workgroups on each XCD (8 words)
+    FLAG_SLICE_XCD = 776, // update slices finished on each XCD in this launch (8 words)
+    FLAG_WORDS = 800
 };
 
 // The XCD this workgroup runs on (hardware register XCC_ID, bits 3:0).
@@ -419,17 +421,41 @@ __device__ __forceinline__ bool grid_barrier_xcd(unsigned* flags, unsigned membe
     return s_stop == 0;
 }
 
-// Counts this workgroup in the launch's XCD census (before the launch's
-// first grid barrier; the census words start at zero).
-__device__ __forceinline__ void xcd_census_add(unsigned* flags) {
-    if (threadIdx.x == 0)
-        __hip_atomic_fetch_add(flags + FLAG_XCD_CENSUS + xcd_id(), 1u, __ATOMIC_RELAXED,
+// Counts this workgroup in the launch's XCD census, and in the census of
+// update-slice workgroups when `slice` (before the launch's first grid
+// barrier; the census words start at zero).
+__device__ __forceinline__ void xcd_census_add(unsigned* flags, bool slice) {
+    if (threadIdx.x == 0) {
+        const unsigned x = xcd_id();
+        __hip_atomic_fetch_add(flags + FLAG_XCD_CENSUS + x, 1u, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
+        if (slice)
+            __hip_atomic_fetch_add(flags + FLAG_SLICE_CENSUS + x, 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Slices finished by this workgroup's XCD are published together: the
+// workgroup waits for its own stores (they are in the XCD's L2) and counts
+// itself relaxed; the last slice of the XCD in this outer iteration writes
+// that L2 back once and adds the XCD's `per_xcd` slices to the count at word
+// `w` that the margin reducers wait on.
+__device__ __forceinline__ void publish_slice_xcd(unsigned* flags, int w, unsigned per_xcd) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned a = __hip_atomic_fetch_add(flags + FLAG_SLICE_XCD + xcd_id(), 1u,
+                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((a + 1u) % per_xcd == 0u) {
+            fence_release_agent();
+            __hip_atomic_fetch_add(flags + w, per_xcd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
 }
 
 // After the first grid barrier: workgroups on this XCD and XCDs in use.
 __device__ __forceinline__ void xcd_census_read(unsigned* flags, unsigned& members,
-                                                unsigned& ngroups) {
+                                                unsigned& ngroups, unsigned& slices) {
     const unsigned me = xcd_id();
     members = 0;
     ngroups = 0;
@@ -439,6 +465,7 @@ __device__ __forceinline__ void xcd_census_read(unsigned* flags, unsigned& membe
         if (c) ++ngroups;
         if (x == me) members = c;
     }
+    slices = atomic_load_relaxed(flags + FLAG_SLICE_CENSUS + me);
 }
 
 }  // namespace casgd

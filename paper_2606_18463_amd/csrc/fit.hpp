@@ -116,12 +116,12 @@ __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigne
     // margins of h0 from the incoming x.
     // The first barrier also completes the XCD census; every later one
     // writes each XCD's L2 back once (grid_barrier_xcd).
-    xcd_census_add(P.flags);
+    xcd_census_add(P.flags, wg < P.nslices && nb > P.nslices);
     gather_rows<DT>(P, h0, gw, ngw);
     if (H > 1) gather_rows<DT>(P, h0 + 1, gw, ngw);
     if (!grid_barrier(P.flags, wg, nb, spin)) return;
-    unsigned xm, xg;
-    xcd_census_read(P.flags, xm, xg);
+    unsigned xm, xg, xs_slices;
+    xcd_census_read(P.flags, xm, xg, xs_slices);
     if (has_gram) gram_phase<DT, GEN>(P, P.G[0], h0, base, base + nb, lds);
     for (int sl = wg; sl < P.nslices; sl += nb)
         update_margin_slice<DT, kNW, GEN>(P, sl, nullptr, 0, false, h0, true, P.rp[0], red, xs, -1);
@@ -183,12 +183,7 @@ __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigne
                 update_margin_slice<DT, kNW, GEN>(P, sl, P.c, h, true, h + 1, more, pick2(P.rp, nxt), red,
                                              xs, snap_row);
             if (wg == 0) phase_mark(P, hh, 4);
-            if (split && wg < P.nslices && more) {
-                __syncthreads();
-                if (threadIdx.x == 0)
-                    __hip_atomic_fetch_add(P.flags + FLAG_SLICES, 1u, __ATOMIC_RELEASE,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-            }
+            if (split && wg < P.nslices && more) publish_slice_xcd(P.flags, FLAG_SLICES, xs_slices);
             if (more2) {
                 if (split) {
                     if (wg >= P.nslices)
