@@ -82,15 +82,20 @@ __global__ __launch_bounds__(kNT) void k_sparse_fit(Sparse S_arg, uint64_t h0, i
 
     if (threadIdx.x == 0 && wg == 0 && S.t_hist) S.t_hist[0] = (int64_t)wall_clock64();
     // Prologue: rows of h0 and h0+1; buckets and Gram of h0; margins of h0.
+    // The first barrier also completes the XCD census; every later one
+    // writes each XCD's L2 back once (grid_barrier_xcd).
+    xcd_census_add(S.flags, false);
     sparse_gather(S, h0, gw, ngw, hrow);
     if (H > 1) sparse_gather(S, h0 + 1, gw, ngw, hrow);
     if (!grid_barrier(S.flags, wg, nb, spin)) return;
+    unsigned xm, xg, xs_unused;
+    xcd_census_read(S.flags, xm, xg, xs_unused);
     sparse_bucket(S, h0, gtid, nthr);
     gram_phase<DT_F32>(S.gram, spick2(S.G, (int)(h0 & 1)), h0, 0, nb, lds);
-    if (!grid_barrier(S.flags, wg, nb, spin)) return;
+    if (!grid_barrier_xcd(S.flags, xm, xg, spin)) return;
     sparse_gram_tail(S, h0, spick2(S.G, (int)(h0 & 1)), gw, ngw, rowbuf);
     sparse_margins(S, h0, reinterpret_cast<float*>(lds));
-    if (!grid_barrier(S.flags, wg, nb, spin)) return;
+    if (!grid_barrier_xcd(S.flags, xm, xg, spin)) return;
 
     for (int64_t hh = 0; hh < H; ++hh) {
         const uint64_t h = h0 + (uint64_t)hh;
@@ -117,7 +122,7 @@ __global__ __launch_bounds__(kNT) void k_sparse_fit(Sparse S_arg, uint64_t h0, i
             if (more2) sparse_gather(S, h + 2, w0, nw, hrow);
             if (wg == R) mark(2);
         }
-        if (!grid_barrier(S.flags, wg, nb, spin)) return;
+        if (!grid_barrier_xcd(S.flags, xm, xg, spin)) return;
         if (wg == 0) mark(3);
         if (wg < R) sparse_pub_clear(S, (wg / K) * NL, min(NL, S.L - (wg / K) * NL), wg % K, K);
         // the wave's scratch for the tail update: its head-row buffer
@@ -126,11 +131,11 @@ __global__ __launch_bounds__(kNT) void k_sparse_fit(Sparse S_arg, uint64_t h0, i
         if (wg == 0) mark(4);
         if (more) sparse_gram_tail(S, h + 1, spick2(S.G, (int)((h + 1) & 1)), gw, ngw, rowbuf);
         if (wg == 0) mark(5);
-        if (!grid_barrier(S.flags, wg, nb, spin)) return;
+        if (!grid_barrier_xcd(S.flags, xm, xg, spin)) return;
         if (wg == 0) mark(6);
         if (more) sparse_margins(S, h + 1, reinterpret_cast<float*>(lds));
         sparse_clear_buckets(S, h, gtid, nthr);
-        if (!grid_barrier(S.flags, wg, nb, spin)) return;
+        if (!grid_barrier_xcd(S.flags, xm, xg, spin)) return;
         if (wg == 0) mark(7);
         if (snap && wg == 0 && threadIdx.x == 0 && S.t_hist)
             S.t_hist[snap_row + 1] = (int64_t)wall_clock64();
