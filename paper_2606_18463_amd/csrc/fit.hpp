@@ -16,22 +16,29 @@ __device__ __forceinline__ void phase_mark(const Dense& P, int64_t hh, int k) {
         P.ptrace[hh * 8 + k] = (int64_t)wall_clock64();
 }
 
-// Margins of outer iteration h from the slices' partial sums: eight lanes per
-// row, lane e adding slices e, e+8, ... in order, then a fixed tree over the
-// eight lanes; times the row scale. Threads gtid of nthreads (multiples of 8).
+// Lanes that reduce one row's partial margins: 8, 16 or 32, from the slice
+// count alone (so a batched problem sums in the same order as a solo one),
+// at most four slices per lane from 32 lanes on.
+__device__ __forceinline__ int margin_lanes(int nslices) {
+    return nslices >= 128 ? 32 : (nslices >= 64 ? 16 : 8);
+}
+
+// Margins of outer iteration h from the slices' partial sums: L lanes per
+// row (margin_lanes), lane e adding slices e, e+L, ... in order, then a fixed
+// tree over the L lanes; times the row scale. Threads gtid of nthreads
+// (multiples of 32).
 template <bool GEN = true>
 __device__ __forceinline__ void reduce_margins(const Dense& P, const float* rp, uint64_t h,
                                                float* r_out, int gtid, int nthreads) {
     const float* sI = pick3(P.sI, slot_of(h));
-    const int e = gtid & 7;
-    // the eight lanes of a group share t, so they run the loop together
-    for (int t = gtid >> 3; t < P.sb; t += nthreads >> 3) {
+    const int L = margin_lanes(P.nslices);
+    const int e = gtid & (L - 1);
+    // the L lanes of a group share t, so they run the loop together
+    for (int t = gtid / L; t < P.sb; t += nthreads / L) {
         float a = 0.f;
-#pragma unroll 8
-        for (int sl = e; sl < P.nslices; sl += 8) a += rp[(int64_t)sl * P.sb + t];
-        a += shfl_xor(a, 1);
-        a += shfl_xor(a, 2);
-        a += shfl_xor(a, 4);
+#pragma unroll 4
+        for (int sl = e; sl < P.nslices; sl += L) a += rp[(int64_t)sl * P.sb + t];
+        for (int off = 1; off < L; off <<= 1) a += shfl_xor(a, off);
         if (e == 0) r_out[t] = e2e_round(a * sI[t], e2e_mode<GEN>(P));
     }
 }
