@@ -280,8 +280,11 @@ __device__ __forceinline__ void raise_flag(unsigned* flags, int which) {
 // they are issued once per workgroup, and the poll itself uses relaxed loads
 // (which read the coherent copy without touching the caches).
 // The wait is bounded: after `spin_limit` polls the timeout flag is raised
-// and every workgroup leaves the barrier (and then the kernel) at once, so a
-// launch can never wait forever. Returns false when the kernel must stop.
+// and the workgroup leaves the kernel; every other one then stops at its
+// next wait (which can no longer complete without it, and which checks the
+// flag every 256 polls), so a launch can never wait forever. A barrier that
+// did complete needs no check of the flag on the way out (one memory round
+// trip less per barrier). Returns false when the kernel must stop.
 __device__ __forceinline__ bool barrier_at(unsigned* flags, int base, unsigned member,
                                            unsigned nblocks, unsigned long long spin_limit) {
     __shared__ int s_stop;
@@ -324,7 +327,6 @@ __device__ __forceinline__ bool barrier_at(unsigned* flags, int base, unsigned m
             }
             fence_acquire_agent();
         }
-        if (atomic_load_relaxed(flags + FLAG_TIMEOUT)) stop = 1;
         s_stop = stop;
     }
     __syncthreads();
@@ -390,9 +392,12 @@ __device__ __forceinline__ bool grid_barrier_xcd(unsigned* flags, unsigned membe
         if (a == members - 1) {
             fence_release_agent();
             atomic_store_relaxed(cnt, 0u);
+            // released just above; only the last arrival at the top acquires
+            // (the other XCDs' releases), before releasing the generation
             const unsigned t =
-                __hip_atomic_fetch_add(top, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (t == ngroups - 1) {
+                fence_acquire_agent();
                 atomic_store_relaxed(top, 0u);
                 atomic_store_release(gen, g0 + 1u);
                 advanced = true;
@@ -414,7 +419,6 @@ __device__ __forceinline__ bool grid_barrier_xcd(unsigned* flags, unsigned membe
             }
             fence_acquire_agent();
         }
-        if (atomic_load_relaxed(flags + FLAG_TIMEOUT)) stop = 1;
         s_stop = stop;
     }
     __syncthreads();
