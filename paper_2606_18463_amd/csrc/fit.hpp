@@ -19,6 +19,16 @@ __device__ __forceinline__ void phase_mark(const Dense& P, int64_t hh, int k) {
 // Lanes that reduce one row's partial margins: 8, 16 or 32, from the slice
 // count alone (so a batched problem sums in the same order as a solo one),
 // at most four slices per lane from 32 lanes on.
+// Column slice handled by slice workgroup wg when every slice workgroup has
+// one (nslices <= nb): the slices of one XCD (workgroups x, x + 8, ...) are
+// contiguous, so the two 64-byte halves of a 128-byte line of a gathered row
+// (neighbouring 16-column slices) are read through the same L2. Partial
+// margins stay indexed by slice, so results do not depend on the mapping.
+__device__ __forceinline__ int slice_of(int wg, int nslices, int nb) {
+    if (nslices > nb || (nslices & 7)) return wg;
+    return (wg & 7) * (nslices >> 3) + (wg >> 3);
+}
+
 __device__ __forceinline__ int margin_lanes(int nslices) {
     return nslices >= 128 ? 32 : (nslices >= 64 ? 16 : 8);
 }
@@ -131,7 +141,8 @@ __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigne
     xcd_census_read(P.flags, xm, xg, xs_slices);
     if (has_gram) gram_phase<DT, GEN>(P, P.G[0], h0, base, base + nb, lds);
     for (int sl = wg; sl < P.nslices; sl += nb)
-        update_margin_slice<DT, kNW, GEN>(P, sl, nullptr, 0, false, h0, true, P.rp[0], red, xs, -1);
+        update_margin_slice<DT, kNW, GEN>(P, slice_of(sl, P.nslices, nb), nullptr, 0, false, h0,
+                                         true, P.rp[0], red, xs, -1);
     if (!grid_barrier_xcd(P.flags, xm, xg, spin)) return;
     for (int64_t hh = 0; hh < H; ++hh) {
         const uint64_t h = h0 + (uint64_t)hh;
@@ -187,8 +198,8 @@ __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigne
             // for the next phase.
             const bool split = nb > P.nslices;
             for (int sl = wg; sl < P.nslices; sl += nb)
-                update_margin_slice<DT, kNW, GEN>(P, sl, P.c, h, true, h + 1, more, pick2(P.rp, nxt), red,
-                                             xs, snap_row);
+                update_margin_slice<DT, kNW, GEN>(P, slice_of(sl, P.nslices, nb), P.c, h, true, h + 1,
+                                                 more, pick2(P.rp, nxt), red, xs, snap_row);
             if (wg == 0) phase_mark(P, hh, 4);
             if (split && wg < P.nslices && more) publish_slice_xcd(P.flags, FLAG_SLICES, xs_slices);
             if (more2) {
@@ -220,8 +231,8 @@ __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigne
                 recurrence<ACC, kNT, GEN>(P, pick2(P.G, cur), pick2(P.rp, cur), h, nullptr, nullptr, cl,
                                      nullptr, dl, pw, tpr);
                 for (int sl = wg; sl < P.nslices; sl += nb)
-                    update_margin_slice<DT, kNW, GEN>(P, sl, cl, h, true, h + 1, more, pick2(P.rp, nxt),
-                                                 red, xs, snap_row);
+                    update_margin_slice<DT, kNW, GEN>(P, slice_of(sl, P.nslices, nb), cl, h, true,
+                                                     h + 1, more, pick2(P.rp, nxt), red, xs, snap_row);
             }
             if (has_gram && more) gram_phase<DT, GEN>(P, pick2(P.G, nxt), h + 1, base, base + nb, lds);
             if (more2) gather_rows<DT>(P, h + 2, gw, ngw);
@@ -238,8 +249,8 @@ __device__ __forceinline__ void fit_body(const Dense& P, int wg, int nb, unsigne
             }
             if (!grid_barrier_xcd(P.flags, xm, xg, spin)) return;
             for (int sl = wg; sl < P.nslices; sl += nb)
-                update_margin_slice<DT, kNW, GEN>(P, sl, P.c, h, true, h + 1, more, pick2(P.rp, nxt), red,
-                                             xs, snap_row);
+                update_margin_slice<DT, kNW, GEN>(P, slice_of(sl, P.nslices, nb), P.c, h, true, h + 1,
+                                                 more, pick2(P.rp, nxt), red, xs, snap_row);
             if (!grid_barrier_xcd(P.flags, xm, xg, spin)) return;
         }
         if (snap && wg == 0 && threadIdx.x == 0 && P.t_hist)
