@@ -727,6 +727,26 @@ __device__ __forceinline__ void gram_phase(const Dense& P, float* Gout, uint64_t
     }
     const int S = P.ksplit;
     const int U = P.gna == 4 ? P.gt : 2 * P.gt;
+    if (S == 1) {
+        // Units in their natural order (the two halves of a tile, then the
+        // tiles of one block row) dealt XCD by XCD: the workgroups of XCD x
+        // (physical indices x mod 8) take consecutive units, so the operand
+        // rows they share are read through one L2. A bijection of the
+        // workgroups, so every unit is computed once, by whichever takes it.
+        const int x = w & 7;
+        int px = 0, fx = lo;
+        for (int y = 0; y < 8; ++y) {
+            const int fy = lo + (y - (lo & 7) + 8) % 8;
+            const int my = fy < hi ? (hi - fy + 7) / 8 : 0;
+            if (y < x) px += my;
+            if (y == x) fx = fy;
+        }
+        for (int u = px + (w - fx) / 8; u < U; u += nw) {
+            if (P.gna == 4) gram_unit<DT, 4, GEN>(P, Gout, h, u, 0, lds);
+            else gram_unit<DT, 2, GEN>(P, Gout, h, u, 0, lds);
+        }
+        return;
+    }
     if (nw >= S) {
         const int c = w % S;
         const int first = lo + ((c - lo % S) + S) % S;
