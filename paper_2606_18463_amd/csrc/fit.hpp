@@ -16,9 +16,6 @@ __device__ __forceinline__ void phase_mark(const Dense& P, int64_t hh, int k) {
         P.ptrace[hh * 8 + k] = (int64_t)wall_clock64();
 }
 
-// Lanes that reduce one row's partial margins: 8, 16 or 32, from the slice
-// count alone (so a batched problem sums in the same order as a solo one),
-// at most four slices per lane from 32 lanes on.
 // Column slice handled by slice workgroup wg when every slice workgroup has
 // one (nslices <= nb): the slices of one XCD (workgroups x, x + 8, ...) are
 // contiguous, so the two 64-byte halves of a 128-byte line of a gathered row
@@ -29,6 +26,9 @@ __device__ __forceinline__ int slice_of(int wg, int nslices, int nb) {
     return (wg & 7) * (nslices >> 3) + (wg >> 3);
 }
 
+// Lanes that reduce one row's partial margins: 8, 16 or 32, from the slice
+// count alone (so a batched problem sums in the same order as a solo one),
+// at most four slices per lane from 32 lanes on.
 __device__ __forceinline__ int margin_lanes(int nslices) {
     return nslices >= 128 ? 32 : (nslices >= 64 ? 16 : 8);
 }
